@@ -1,0 +1,190 @@
+/*
+ * ssf.h -- C ABI of libssf, the MI355X (gfx950) split-step Fourier library.
+ *
+ * libssf propagates a complex wavefunction psi on a periodic 3-D grid with
+ * the Fourier split-operator method used for the three-dimensional waveguide
+ * simulations of Morgan et al., "Coherent transport by adiabatic passage on
+ * atom chips" (arXiv:1309.2451), Sec. IV (time step = 3-D Fourier transforms
+ * plus pointwise multiplications by the exponentiated potential and kinetic
+ * operators; momentum grid bounded by p_max = pi N / L) and Sec. V
+ * (imaginary-time ground state, populations of the three guides).
+ * Units: hbar = m = 1, so H = -1/2 laplacian + V.
+ *
+ * One Strang step (real time, dt):
+ *     psi <- exp(-i V dt/2) IFFT[ exp(-i k^2 dt/2) FFT[ exp(-i V dt/2) psi ] ]
+ * Imaginary time replaces exp(-i x) by exp(-x) and renormalises every step.
+ *
+ * Conventions
+ *   - Grids: n = {Nx, Ny, Nz}; axis a samples lo[a] + j (hi[a]-lo[a])/n[a],
+ *     j = 0..n[a]-1 (periodic, hi excluded).  Each n[a] must be one of the
+ *     supported transform lengths (ssf_supported_length).
+ *   - Fields live in device memory (HBM), shape (Nz, Ny, Nx), x fastest,
+ *     interleaved complex: SSF_C64 = 2 x float (8 B), SSF_C128 = 2 x double
+ *     (16 B), contiguous, aligned to the element size.  In complex64 mode all
+ *     arithmetic is FP64 in registers and values are rounded once per pass.
+ *   - FFT: forward sum_j x_j exp(-2 pi i j k / n), inverse with +i, both
+ *     unnormalised in ssf_fft; the step applies 1/(Nx Ny Nz) itself.
+ *   - Wavenumbers: k_j = (2 pi / L)(j if 2j < n else j - n).
+ *
+ * Ownership: the caller owns every device buffer passed in (psi, lambda,
+ * potential tables, observation and gradient buffers, checkpoints); the
+ * library never frees them.  The handle owns its tables and workspace.
+ * Potential tables set with ssf_set_potential_table are borrowed and must
+ * stay alive while steps run.
+ *
+ * Streams: every call enqueues on the handle's HIP stream and returns without
+ * waiting, except where noted (ssf_obs_read, ssf_sync, ssf_destroy, and the
+ * first use of a new (dt, time) pair, which builds kinetic tables on the
+ * device asynchronously but may allocate).  Calls on one handle must come from
+ * one thread at a time.
+ *
+ * Errors: every function returns SSF_OK (0) or a negative ssf_status and
+ * never aborts.  ssf_last_error() gives a thread-local message.  Asynchronous
+ * device faults surface at the next synchronising call.
+ */
+#ifndef SSF_H
+#define SSF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ssf_status;
+#define SSF_OK 0
+#define SSF_E_INVALID (-1)     /* bad argument: null, shape, alignment, dtype, dt, count */
+#define SSF_E_UNSUPPORTED (-2) /* transform length not built into the library */
+#define SSF_E_NOMEM (-3)       /* device allocation failed */
+#define SSF_E_NODEVICE (-4)    /* no HIP device visible */
+#define SSF_E_DEVICE (-5)      /* HIP runtime error (message in ssf_last_error) */
+#define SSF_E_NONFINITE (-6)   /* an observation recorded a non-finite norm */
+
+#define SSF_C64 1
+#define SSF_C128 2
+#define SSF_REAL 0
+#define SSF_IMAG 1
+
+typedef struct ssf_handle ssf_handle;
+
+typedef struct ssf_grid_desc {
+  int32_t n[3];    /* Nx, Ny, Nz */
+  double lo[3];    /* box start per axis */
+  double hi[3];    /* box end per axis (excluded) */
+} ssf_grid_desc;
+
+/* Three-guide potential (Gaussian stand-in for the chip's guides, Sec. III):
+ * V(x,y,z) = - sum_g v0[g] exp(-((x - xc[g][z])^2 + y^2) / (2 sigma[g]^2)). */
+typedef struct ssf_ctap_desc {
+  int32_t nguides;     /* 1..3 */
+  double v0[3];        /* well depths */
+  double sigma[3];     /* widths (> 0) */
+  const double* xc;    /* host, (nguides, Nz) guide centres, copied by the call */
+} ssf_ctap_desc;
+
+/* One observation (Sec. V, Figs. 4 and 6: guide populations). */
+typedef struct ssf_obs {
+  double norm;       /* sum |psi|^2 dV */
+  double mean[3];    /* sum r_a |psi|^2 dV (first moments, not divided by norm) */
+  double pop[3];     /* P1: x < x_lo, P2: x_lo <= x <= x_hi, P3: x > x_hi */
+  double epot;       /* sum V |psi|^2 dV */
+  double energy;     /* ssf_observables: <H>; imaginary-time step: -ln(norm ratio)/dt; else 0 */
+  int64_t step;      /* steps completed within the call when recorded */
+  int32_t flags;     /* bit 0: non-finite norm */
+  int32_t reserved;
+} ssf_obs;
+
+/* Nonzero if n is a transform length built into the library. */
+int32_t ssf_supported_length(int32_t n);
+
+/* Create a handle for one grid and storage type (SSF_C64 / SSF_C128) on the
+ * current HIP device, enqueueing on `hip_stream` (NULL = default stream).
+ * Allocates tables and workspace (tens of bytes per grid point of x-z plane,
+ * plus FP64 partial sums).  Errors: INVALID (null, n < 1, hi <= lo, dtype),
+ * UNSUPPORTED (length), NODEVICE, NOMEM, DEVICE. */
+ssf_status ssf_create(const ssf_grid_desc* grid, int32_t dtype, void* hip_stream, ssf_handle** out);
+/* Synchronises the handle's stream, then frees what the handle owns. */
+ssf_status ssf_destroy(ssf_handle* h);
+ssf_status ssf_set_stream(ssf_handle* h, void* hip_stream);
+
+/* Borrow a device potential table (Nz, Ny, Nx): FP64 if v_is_f64, else FP32. */
+ssf_status ssf_set_potential_table(ssf_handle* h, const void* v_dev, int32_t v_is_f64);
+/* Build the three-guide potential tables on the device (synchronous upload).
+ * Errors: INVALID (nguides outside 1..3, sigma <= 0, null xc). */
+ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d);
+/* Remove the potential (free particle). */
+ssf_status ssf_clear_potential(ssf_handle* h);
+/* Guide regions for the populations: P1 counts grid points with x < x_lo,
+ * P3 those with x > x_hi (strict), P2 the rest. */
+ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi);
+/* 0: one Strang step = 5 passes; 1 (default): consecutive steps without an
+ * observation between them share one x pass (exp(-i V dt) between the inverse
+ * and the next forward x transform), 4 passes per step.  Same result up to
+ * rounding. */
+ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
+
+/* Pass timing for measurement: while on, every pass launch is bracketed by
+ * a pair of HIP events on the handle's stream.  ssf_timing_read synchronises
+ * the stream and returns, per pass kind, the summed kernel time in ms and the
+ * number of launches since timing was switched on or last read, then resets.
+ * Kinds (6 entries): 0 x forward, 1 x inverse, 2 x inverse-phase-forward,
+ * 3 y/z forward, 4 y/z inverse, 5 z forward-kinetic-inverse. */
+ssf_status ssf_set_timing(ssf_handle* h, int32_t on);
+ssf_status ssf_timing_read(ssf_handle* h, double* ms_total, int64_t* launches);
+
+/* nsteps Strang steps of psi (in place) with time step dt (nonzero, finite;
+ * dt < 0 runs backwards; imaginary time needs dt > 0).  time = SSF_REAL or
+ * SSF_IMAG.  If obs_every > 0 and obs_dev != NULL, after every obs_every-th
+ * step an ssf_obs is written to obs_dev[step/obs_every - 1] (caller provides
+ * nsteps/obs_every slots).  Imaginary time renormalises to norm 1 after every
+ * step; the input is first scaled to norm 1.  No allocation after the first
+ * call with a given (dt, time); no synchronisation. */
+ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time,
+                    int64_t obs_every, ssf_obs* obs_dev);
+
+/* Unnormalised 1-D transforms of psi (in place) along the axes in axis_mask
+ * (bit 0 = x, 1 = y, 2 = z); inverse != 0 uses exp(+...). */
+ssf_status ssf_fft(ssf_handle* h, void* psi, int32_t axis_mask, int32_t inverse);
+
+/* Observables of psi into obs_dev[0], including <H> = sum (k^2/2)|FFT psi|^2 dV/N
+ * + sum V |psi|^2 dV.  Allocates a field-sized workspace on first use. */
+ssf_status ssf_observables(ssf_handle* h, const void* psi, ssf_obs* obs_dev);
+/* Copy count observations to the host (synchronises the stream).  Returns
+ * SSF_E_NONFINITE if any copied record has flags bit 0 set. */
+ssf_status ssf_obs_read(ssf_handle* h, const ssf_obs* obs_dev, ssf_obs* host, int64_t count);
+/* Wait for the handle's stream; reports pending asynchronous errors. */
+ssf_status ssf_sync(ssf_handle* h);
+
+/* Real-time propagation with checkpoints: before the steps s*every
+ * (s = 0 .. ceil(nsteps/every)-1) psi is copied to slot s of ckpt_dev
+ * (field-sized slots, contiguous).  Steps are never merged, so
+ * ssf_step_seq from a checkpoint reproduces the same states bitwise. */
+ssf_status ssf_step_ckpt(ssf_handle* h, void* psi, int64_t nsteps, double dt, int64_t every,
+                         void* ckpt_dev);
+/* seq_dev slot 0 = psi0, slot s = state after s real-time steps, s <= nsteps
+ * (nsteps + 1 field-sized slots). */
+ssf_status ssf_step_seq(ssf_handle* h, const void* psi0, int64_t nsteps, double dt, void* seq_dev);
+
+/* Adjoint of the final target population F = sum_{x > x_hi} |psi_N|^2 dV
+ * (Sec. V, Fig. 6: transfer fidelity) with respect to the guide centres
+ * xc[g][z] of the potential set by ssf_set_potential_ctap.
+ * ssf_adjoint_init: lambda = psi where x > x_hi, 0 elsewhere.
+ * ssf_adjoint_segment: with seq_dev the nsteps+1 states of one segment
+ * (ssf_step_seq), walks the segment backwards: lambda <- U(-dt) lambda, and
+ * for every potential half-step adds dt sum dV/dxc_g Im(conj(lambda) psi) dV
+ * to G_dev[g][z] (FP64, (nguides, Nz), accumulated, caller zeroes it). */
+ssf_status ssf_adjoint_init(ssf_handle* h, const void* psi, void* lambda);
+ssf_status ssf_adjoint_segment(ssf_handle* h, void* lambda, const void* seq_dev, int64_t nsteps,
+                               double dt, double* G_dev);
+
+/* Host helper: clamped uniform cubic B-spline basis on [a, b] with M >= 4
+ * functions evaluated at z[0..nz-1]; B_out is (nz, M) row-major, FP64. */
+ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int32_t nz, double* B_out);
+
+const char* ssf_status_string(ssf_status s);
+const char* ssf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSF_H */

@@ -1,0 +1,217 @@
+"""MI355X split-step Fourier propagation of the 3-D Schroedinger equation.
+
+Python face of libssf (include/ssf.h).  Fields are torch tensors on the GPU,
+shape (Nz, Ny, Nx), dtype complex64 or complex128, contiguous; every method
+forwards to the C ABI function of the same name with the tensors' device
+pointers and torch's current HIP stream.  The split-step arithmetic runs in
+the library's HIP kernels only.
+
+Method: Morgan et al., "Coherent transport by adiabatic passage on atom
+chips", arXiv:1309.2451 -- Sec. IV (Fourier split-operator time step,
+p_max = pi N / L), Sec. V (imaginary-time transverse ground state, guide
+populations and final transfer fidelity).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _ssf
+from ._ssf import OBS_DTYPE, SSF_C64, SSF_C128, SSF_IMAG, SSF_REAL, SSFError
+
+__all__ = ["Solver", "SSFError", "OBS_DTYPE", "supported_length", "bspline_basis", "load"]
+
+
+def load():
+    return _ssf.load()
+
+
+def supported_length(n: int) -> bool:
+    return bool(_ssf.load().ssf_supported_length(int(n)))
+
+
+def bspline_basis(M, a, b, z):
+    """(len(z), M) clamped uniform cubic B-spline basis on [a, b] (host, FP64)."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    B = np.empty((z.shape[0], int(M)), dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _ssf.call("ssf_bspline_basis", int(M), float(a), float(b), z.ctypes.data_as(dp), z.shape[0],
+              B.ctypes.data_as(dp))
+    return B
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """One grid + storage type on one GPU (an ssf_handle).
+
+    n = (Nx, Ny, Nz); lo, hi = box per axis; dtype "c64" or "c128".
+    """
+
+    def __init__(self, n, lo, hi, dtype="c128", device=None):
+        torch = _torch()
+        self.torch = torch
+        self.n = tuple(int(v) for v in n)
+        self.lo = tuple(float(v) for v in lo)
+        self.hi = tuple(float(v) for v in hi)
+        self.dtype = {"c64": SSF_C64, "c128": SSF_C128}[dtype]
+        self.tdtype = torch.complex64 if self.dtype == SSF_C64 else torch.complex128
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.shape = (self.n[2], self.n[1], self.n[0])
+        g = _ssf.ssf_grid_desc()
+        for a in range(3):
+            g.n[a], g.lo[a], g.hi[a] = self.n[a], self.lo[a], self.hi[a]
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _ssf.call("ssf_create", ctypes.byref(g), self.dtype, ctypes.c_void_p(stream), ctypes.byref(h))
+        self.h = h
+        self._keep = {}
+
+    # -- plumbing -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            _ssf.call("ssf_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        _ssf.call("ssf_set_stream", self.h, ctypes.c_void_p(s))
+
+    def _field(self, t, name="psi"):
+        if t.dtype != self.tdtype or tuple(t.shape[-3:]) != self.shape or not t.is_contiguous() \
+                or t.device != self.device:
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s (got %s %s %s)"
+                             % (name, self.tdtype, self.shape, self.device, t.dtype, tuple(t.shape), t.device))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self, *lead):
+        return self.torch.empty(*lead, *self.shape, dtype=self.tdtype, device=self.device)
+
+    def obs_buffer(self, count):
+        return self.torch.zeros(max(int(count), 1) * OBS_DTYPE.itemsize, dtype=self.torch.uint8, device=self.device)
+
+    def read_obs(self, buf, count):
+        host = np.zeros(int(count), dtype=OBS_DTYPE)
+        if count:
+            self._sync_stream()
+            _ssf.call("ssf_obs_read", self.h, ctypes.c_void_p(buf.data_ptr()),
+                      ctypes.c_void_p(host.ctypes.data), int(count))
+        return host
+
+    # -- configuration ----------------------------------------------------------
+    def set_potential_table(self, V):
+        torch = self.torch
+        if V.dtype not in (torch.float64, torch.float32) or tuple(V.shape) != self.shape or not V.is_contiguous():
+            raise ValueError("potential table must be a contiguous float32/float64 tensor of shape %s" % (self.shape,))
+        self._keep["V"] = V
+        _ssf.call("ssf_set_potential_table", self.h, ctypes.c_void_p(V.data_ptr()), 1 if V.dtype == torch.float64 else 0)
+
+    def set_guides(self, v0, sigma, xc):
+        xc = np.ascontiguousarray(xc, dtype=np.float64)
+        d = _ssf.ssf_ctap_desc()
+        d.nguides = xc.shape[0]
+        for g in range(d.nguides):
+            d.v0[g] = float(v0[g])
+            d.sigma[g] = float(sigma[g])
+        if xc.shape != (d.nguides, self.n[2]):
+            raise ValueError("xc must be (nguides, Nz)")
+        d.xc = xc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._sync_stream()
+        _ssf.call("ssf_set_potential_ctap", self.h, ctypes.byref(d))
+        self.nguides = d.nguides
+
+    def clear_potential(self):
+        _ssf.call("ssf_clear_potential", self.h)
+
+    def set_partition(self, x_lo, x_hi):
+        _ssf.call("ssf_set_partition", self.h, float(x_lo), float(x_hi))
+
+    def set_fusion(self, on: bool):
+        _ssf.call("ssf_set_fusion", self.h, 1 if on else 0)
+
+    PASS_KINDS = ("x_fwd", "x_inv", "x_inv_phase_fwd", "yz_fwd", "yz_inv", "z_fwd_kin_inv")
+
+    def set_timing(self, on: bool):
+        _ssf.call("ssf_set_timing", self.h, 1 if on else 0)
+
+    def timing_read(self):
+        """{pass kind: (total ms, launches)} since timing was enabled or last read."""
+        self._sync_stream()
+        ms = np.zeros(6, dtype=np.float64)
+        cnt = np.zeros(6, dtype=np.int64)
+        _ssf.call("ssf_timing_read", self.h, ctypes.c_void_p(ms.ctypes.data), ctypes.c_void_p(cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PASS_KINDS)}
+
+    # -- the path ----------------------------------------------------------------
+    def step(self, psi, nsteps, dt, imag=False, obs_every=0, obs_buf=None):
+        """nsteps Strang steps in place.  Returns the observation records
+        (numpy, OBS_DTYPE) if obs_every > 0, else None.  With obs_buf given the
+        records stay on the device (no synchronisation) and None is returned."""
+        self._sync_stream()
+        p = self._field(psi)
+        nobs = (int(nsteps) // int(obs_every)) if obs_every else 0
+        buf = obs_buf if obs_buf is not None else (self.obs_buffer(nobs) if nobs else None)
+        _ssf.call("ssf_step", self.h, p, int(nsteps), float(dt), SSF_IMAG if imag else SSF_REAL,
+                  int(obs_every) if nobs else 0, ctypes.c_void_p(buf.data_ptr()) if buf is not None else None)
+        if nobs and obs_buf is None:
+            return self.read_obs(buf, nobs)
+        return None
+
+    def fft(self, psi, axes=(0, 1, 2), inverse=False):
+        self._sync_stream()
+        mask = 0
+        for a in axes:
+            mask |= 1 << int(a)
+        _ssf.call("ssf_fft", self.h, self._field(psi), mask, 1 if inverse else 0)
+
+    def observables(self, psi):
+        self._sync_stream()
+        buf = self.obs_buffer(1)
+        _ssf.call("ssf_observables", self.h, self._field(psi), ctypes.c_void_p(buf.data_ptr()))
+        return self.read_obs(buf, 1)[0]
+
+    def step_ckpt(self, psi, nsteps, dt, every, ckpt):
+        self._sync_stream()
+        nslots = -(-int(nsteps) // int(every))
+        if ckpt.shape[0] < nslots:
+            raise ValueError("checkpoint buffer needs %d slots" % nslots)
+        self._field(ckpt[0], "ckpt")
+        _ssf.call("ssf_step_ckpt", self.h, self._field(psi), int(nsteps), float(dt), int(every),
+                  ctypes.c_void_p(ckpt.data_ptr()))
+
+    def step_seq(self, psi0, nsteps, dt, seq):
+        self._sync_stream()
+        if seq.shape[0] < int(nsteps) + 1:
+            raise ValueError("sequence buffer needs nsteps + 1 slots")
+        self._field(seq[0], "seq")
+        _ssf.call("ssf_step_seq", self.h, self._field(psi0, "psi0"), int(nsteps), float(dt),
+                  ctypes.c_void_p(seq.data_ptr()))
+
+    def adjoint_init(self, psi, lam):
+        self._sync_stream()
+        _ssf.call("ssf_adjoint_init", self.h, self._field(psi), self._field(lam, "lambda"))
+
+    def adjoint_segment(self, lam, seq, nsteps, dt, G):
+        torch = self.torch
+        if G.dtype != torch.float64 or not G.is_contiguous() or G.numel() < self.nguides * self.n[2]:
+            raise ValueError("G must be a contiguous float64 tensor with nguides * Nz entries")
+        if seq.shape[0] < int(nsteps) + 1:
+            raise ValueError("sequence buffer needs nsteps + 1 slots")
+        self._field(seq[0], "seq")
+        self._sync_stream()
+        _ssf.call("ssf_adjoint_segment", self.h, self._field(lam, "lambda"), ctypes.c_void_p(seq.data_ptr()),
+                  int(nsteps), float(dt), ctypes.c_void_p(G.data_ptr()))
+
+    def sync(self):
+        _ssf.call("ssf_sync", self.h)

@@ -1,0 +1,650 @@
+// Pencil-pass kernels of the 3-D split-operator step for CDNA4 (gfx950).
+//
+// One launch applies a 1-D DFT of length N to every pencil along one axis of
+// a (nz, ny, nx) complex field, optionally fused with the pointwise factors of
+// the Fourier split-operator method (Morgan et al., arXiv:1309.2451, Sec. IV):
+// the potential phase exp(-i V c) on the way in or out, and -- for a fused
+// forward/inverse pass -- the kinetic phase exp(-i k^2 dt/2) (or the potential
+// phase) between the two transforms, so the factors cost no extra HBM sweep.
+//
+// Transform: Stockham autosort, stage radices from Plan<N>.  Stage s with
+// radix r and p = product of the earlier radices turns input i + m N/r
+// (m < r) into output j + q p with k = i mod p, j = (i - k) r + k, after
+// multiplying input m by exp(sign 2 pi i m k / (p r)).  The first stage reads
+// global memory and the last one writes it, both coalesced; the stages in
+// between exchange through LDS.  Arithmetic is FP64 in registers whatever the
+// storage type, so complex64 storage is rounded once per pass, at the store.
+//
+// Thread layout: a workgroup owns P pencils and every thread owns E values
+// (E/r butterflies per stage).  Contiguous (x) passes map consecutive threads
+// to consecutive butterflies of one pencil; strided (y, z) passes map them to
+// consecutive x columns of a px-wide tile, so each global access is a run of
+// px * sizeof(storage) contiguous bytes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "ssf_internal.hpp"
+
+namespace ssf {
+
+// ---------------------------------------------------------------------------
+// Plans: stage radices (forward order) and values per thread E, a common
+// multiple of the radices.
+// ---------------------------------------------------------------------------
+template <int N> struct Plan;
+#define SSF_PLAN(NN, EE, ...)                                              \
+  template <> struct Plan<NN> {                                            \
+    static constexpr int E = EE;                                           \
+    static constexpr int R[] = {__VA_ARGS__};                              \
+    static constexpr int S = sizeof(R) / sizeof(int);                      \
+  };
+SSF_PLAN(1, 1, 1)
+SSF_PLAN(2, 2, 2)
+SSF_PLAN(4, 4, 4)
+SSF_PLAN(8, 8, 8)
+SSF_PLAN(16, 16, 16)
+SSF_PLAN(32, 8, 4, 8)
+SSF_PLAN(64, 8, 8, 8)
+SSF_PLAN(128, 8, 4, 4, 8)
+SSF_PLAN(256, 8, 4, 8, 8)
+SSF_PLAN(512, 8, 8, 8, 8)
+SSF_PLAN(1024, 8, 4, 4, 8, 8)
+SSF_PLAN(12, 12, 3, 4)
+SSF_PLAN(24, 12, 2, 3, 4)
+SSF_PLAN(48, 12, 3, 4, 4)
+SSF_PLAN(96, 12, 4, 4, 2, 3)
+SSF_PLAN(192, 12, 3, 4, 4, 4)
+SSF_PLAN(384, 24, 3, 4, 4, 8)
+SSF_PLAN(768, 24, 3, 4, 8, 8)
+SSF_PLAN(20, 20, 4, 5)
+SSF_PLAN(40, 20, 2, 4, 5)
+SSF_PLAN(80, 20, 4, 4, 5)
+SSF_PLAN(160, 20, 2, 4, 4, 5)
+SSF_PLAN(320, 20, 4, 4, 4, 5)
+SSF_PLAN(640, 20, 2, 4, 4, 4, 5)
+#undef SSF_PLAN
+
+template <class PL, bool REV> struct Order {
+  static constexpr int r(int s) { return REV ? PL::R[PL::S - 1 - s] : PL::R[s]; }
+  static constexpr int p(int s) {
+    int q = 1;
+    for (int t = 0; t < s; ++t) q *= r(t);
+    return q;
+  }
+};
+
+// Tile shapes.  LDS holds P pencils of N FP64 complex values.
+constexpr int LDS_CAP_ELEMS = 8192;       // 128 KiB of double2
+template <int N> struct Shape {
+  static constexpr int E = Plan<N>::E;
+  static constexpr int sx(int dt) {        // strided tile width in x
+    int px = dt == 0 ? 16 : 8;             // 128 B of storage per row segment
+    while (px > 1 && px * N > LDS_CAP_ELEMS) px /= 2;
+    return px;
+  }
+  static constexpr int so(int dt) {        // strided tile depth (outer pencils)
+    int po = 256 * E / (N * sx(dt));
+    if (po < 1) po = 1;
+    while (po > 1 && sx(dt) * po * N > LDS_CAP_ELEMS) po /= 2;
+    while (po > 1 && sx(dt) * po * N / E > 1024) po /= 2;
+    return po;
+  }
+  static constexpr int ldrow() { return N + N / 8 + (N >= 8 ? 0 : 0); }
+  static constexpr int cr() {              // contiguous rows per workgroup
+    int rows = 256 * E / N;
+    if (rows < 1) rows = 1;
+    while (rows > 1 && rows * ldrow() > 4096) rows /= 2;
+    return rows;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Complex helpers (FP64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV> __device__ __forceinline__ double2 mul_mi(double2 a) {
+  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+// multiply by exp(-/+ i pi/4) * sqrt2 ... as rotation by w8 = exp(-/+ 2 pi i / 8)
+constexpr double SQRT1_2 = 0.70710678118654752440084436210485;
+template <bool INV> __device__ __forceinline__ double2 mul_w8_1(double2 a) {
+  // fwd: (1 - i)/sqrt2, inv: (1 + i)/sqrt2
+  return INV ? make_double2((a.x - a.y) * SQRT1_2, (a.x + a.y) * SQRT1_2)
+             : make_double2((a.x + a.y) * SQRT1_2, (a.y - a.x) * SQRT1_2);
+}
+template <bool INV> __device__ __forceinline__ double2 mul_w8_3(double2 a) {
+  // fwd: (-1 - i)/sqrt2, inv: (-1 + i)/sqrt2
+  return INV ? make_double2((-a.x - a.y) * SQRT1_2, (a.x - a.y) * SQRT1_2)
+             : make_double2((a.y - a.x) * SQRT1_2, (-a.x - a.y) * SQRT1_2);
+}
+
+// Storage conversions.
+__device__ __forceinline__ double2 ld2(const float2* p) { float2 f = *p; return make_double2(f.x, f.y); }
+__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+// Value as it is after rounding to storage (for reductions that must see the stored field).
+__device__ __forceinline__ double2 rounded(double2 v, const float2*) { return make_double2((double)(float)v.x, (double)(float)v.y); }
+__device__ __forceinline__ double2 rounded(double2 v, const double2*) { return v; }
+
+// ---------------------------------------------------------------------------
+// Small DFTs: y_q = sum_m x_m exp(sign 2 pi i m q / r), in place, sign = -1
+// forward and +1 inverse.
+// ---------------------------------------------------------------------------
+template <int R, bool INV> struct Bfly;
+
+template <bool INV> struct Bfly<1, INV> { __device__ static void run(double2*) {} };
+
+template <bool INV> struct Bfly<2, INV> {
+  __device__ static void run(double2* x) {
+    double2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <bool INV> struct Bfly<4, INV> {
+  __device__ static void run(double2* x) {
+    double2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+    double2 t2 = cadd(x[1], x[3]), t3 = mul_mi<INV>(csub(x[1], x[3]));
+    x[0] = cadd(t0, t2);
+    x[2] = csub(t0, t2);
+    x[1] = cadd(t1, t3);
+    x[3] = csub(t1, t3);
+  }
+};
+
+template <bool INV> struct Bfly<8, INV> {
+  __device__ static void run(double2* x) {
+    double2 e[4] = {x[0], x[2], x[4], x[6]};
+    double2 o[4] = {x[1], x[3], x[5], x[7]};
+    Bfly<4, INV>::run(e);
+    Bfly<4, INV>::run(o);
+    o[1] = mul_w8_1<INV>(o[1]);
+    o[2] = mul_mi<INV>(o[2]);
+    o[3] = mul_w8_3<INV>(o[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[q] = cadd(e[q], o[q]);
+      x[q + 4] = csub(e[q], o[q]);
+    }
+  }
+};
+
+// cos and sin of 2 pi q / 16, q = 0..7
+__device__ constexpr double C16[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                      0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+__device__ constexpr double S16[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                      1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+
+template <bool INV> struct Bfly<16, INV> {
+  __device__ static void run(double2* x) {
+    double2 e[8], o[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) { e[q] = x[2 * q]; o[q] = x[2 * q + 1]; }
+    Bfly<8, INV>::run(e);
+    Bfly<8, INV>::run(o);
+#pragma unroll
+    for (int q = 1; q < 8; ++q) {
+      double2 w = make_double2(C16[q], INV ? S16[q] : -S16[q]);
+      o[q] = cmul(o[q], w);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      x[q] = cadd(e[q], o[q]);
+      x[q + 8] = csub(e[q], o[q]);
+    }
+  }
+};
+
+constexpr double SIN_2PI_3 = 0.86602540378443864676372317075294;  // sqrt(3)/2
+template <bool INV> struct Bfly<3, INV> {
+  __device__ static void run(double2* x) {
+    double2 t = cadd(x[1], x[2]);
+    double2 s = csub(x[1], x[2]);
+    double2 a = make_double2(x[0].x - 0.5 * t.x, x[0].y - 0.5 * t.y);
+    // fwd: y1 = a - i (sqrt3/2) s, y2 = a + i (sqrt3/2) s
+    double2 b = mul_mi<INV>(cscale(s, SIN_2PI_3));
+    x[0] = cadd(x[0], t);
+    x[1] = cadd(a, b);
+    x[2] = csub(a, b);
+  }
+};
+
+constexpr double C1_5 = 0.30901699437494742410229341718282;   // cos(2 pi / 5)
+constexpr double C2_5 = -0.80901699437494742410229341718282;  // cos(4 pi / 5)
+constexpr double S1_5 = 0.95105651629515357211643933337938;   // sin(2 pi / 5)
+constexpr double S2_5 = 0.58778525229247312916870595463907;   // sin(4 pi / 5)
+template <bool INV> struct Bfly<5, INV> {
+  __device__ static void run(double2* x) {
+    double2 a1 = cadd(x[1], x[4]), a2 = cadd(x[2], x[3]);
+    double2 b1 = csub(x[1], x[4]), b2 = csub(x[2], x[3]);
+    double2 x0 = x[0];
+    double2 r1 = make_double2(x0.x + C1_5 * a1.x + C2_5 * a2.x, x0.y + C1_5 * a1.y + C2_5 * a2.y);
+    double2 r2 = make_double2(x0.x + C2_5 * a1.x + C1_5 * a2.x, x0.y + C2_5 * a1.y + C1_5 * a2.y);
+    double2 i1 = make_double2(S1_5 * b1.x + S2_5 * b2.x, S1_5 * b1.y + S2_5 * b2.y);
+    double2 i2 = make_double2(S2_5 * b1.x - S1_5 * b2.x, S2_5 * b1.y - S1_5 * b2.y);
+    // fwd: y1 = r1 - i i1, y4 = r1 + i i1, y2 = r2 - i i2, y3 = r2 + i i2
+    double2 j1 = mul_mi<INV>(i1), j2 = mul_mi<INV>(i2);
+    x[0] = cadd(x0, cadd(a1, a2));
+    x[1] = cadd(r1, j1);
+    x[4] = csub(r1, j1);
+    x[2] = cadd(r2, j2);
+    x[3] = csub(r2, j2);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Phase factors.  theta = V * c.  Real time: exp(-i theta); imaginary time:
+// exp(-theta).
+//
+// sincos: Cody-Waite reduction by pi/2 with a two-part constant (the product
+// q * (pi/2)_hi is exact inside the fused multiply-add), then the Taylor
+// series of sin to degree 17 and of cos to degree 18 on |r| <= pi/4, whose
+// truncation error is below 5e-17; quadrant by q mod 4.  About 1 ulp for
+// |theta| up to 1e5 (checked against long-double sin/cos on the host).
+// ---------------------------------------------------------------------------
+constexpr double TWO_OVER_PI = 0.63661977236758134308;
+constexpr double PIO2_HI = 1.5707963267948966192;       // nearest double to pi/2
+constexpr double PIO2_LO = 6.123233995736766036e-17;    // pi/2 - PIO2_HI
+__device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
+  const double q = rint(t * TWO_OVER_PI);
+  double r = fma(-q, PIO2_HI, t);
+  r = fma(-q, PIO2_LO, r);
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;            // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);       // 1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);           // 1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);            // 1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);               // 1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);                // 1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);                  // 1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);                   // 1/3!
+  const double sr = fma(ps * r2, r, r);
+  double pc = 1.0 / 6402373705728000.0;           // 1/18!
+  pc = fma(pc, r2, -1.0 / 20922789888000.0);      // 1/16!
+  pc = fma(pc, r2, 1.0 / 87178291200.0);          // 1/14!
+  pc = fma(pc, r2, -1.0 / 479001600.0);           // 1/12!
+  pc = fma(pc, r2, 1.0 / 3628800.0);              // 1/10!
+  pc = fma(pc, r2, -1.0 / 40320.0);               // 1/8!
+  pc = fma(pc, r2, 1.0 / 720.0);                  // 1/6!
+  pc = fma(pc, r2, -1.0 / 24.0);                  // 1/4!
+  pc = fma(pc, r2, 0.5);                          // 1/2!
+  const double cr = fma(-pc, r2, 1.0);
+  const int k = (int)((long long)q & 3);
+  double ss = sr, cc = cr;
+  if (k == 1) { ss = cr; cc = -sr; }
+  else if (k == 2) { ss = -sr; cc = -cr; }
+  else if (k == 3) { ss = -cr; cc = sr; }
+  *s = ss;
+  *c = cc;
+}
+__device__ __forceinline__ double2 phase_factor(double theta, int imag) {
+  if (imag) return make_double2(exp(-theta), 0.0);
+  double s, c;
+  sincos_fast(theta, &s, &c);
+  return make_double2(c, -s);
+}
+
+__device__ __forceinline__ double potential_at(const PassArgs& a, int x, int y, int z) {
+  switch (a.vkind) {
+    case V_TAB64: return ((const double*)a.vtab)[((long long)z * a.ny + y) * a.nx + x];
+    case V_TAB32: return (double)((const float*)a.vtab)[((long long)z * a.ny + y) * a.nx + x];
+    case V_CTAP: {
+      double v = 0.0;
+      for (int j = 0; j < a.nguides; ++j)
+        v -= a.ctapA[((long long)j * a.nz + z) * a.nx + x] * a.ctapB[(long long)j * a.ny + y];
+      return v;
+    }
+    default: return 0.0;
+  }
+}
+
+// Workgroup sum of NV doubles per thread; thread 0 writes them to dst.
+template <int WG, int NV>
+__device__ __forceinline__ void block_sum(double (&acc)[NV], double* dst, double* red) {
+  constexpr int NW = (WG + 63) / 64;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    acc[q] = v;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[wave * NV + q] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w * NV + threadIdx.x];
+    dst[threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The pass kernel.
+// ---------------------------------------------------------------------------
+template <typename S, int N, int PX, int PO, bool CONTIG>
+struct PassGeom {
+  using PL = Plan<N>;
+  static constexpr int P = PX * PO;
+  static constexpr int E = PL::E;
+  static constexpr int WG = P * N / E;
+  static constexpr int LDROW = Shape<N>::ldrow();
+  static constexpr int LDS = PL::S > 1 ? (CONTIG ? P * LDROW : P * N) : 1;
+
+  // butterfly g of a radix-r stage -> (pencil b, butterfly i within the pencil)
+  template <int r> __device__ static __forceinline__ void map(int g, int& b, int& i) {
+    if constexpr (CONTIG) { i = g % (N / r); b = g / (N / r); }
+    else { b = g % P; i = g / P; }
+  }
+  __device__ static __forceinline__ int lidx(int b, int n) {
+    if constexpr (CONTIG) return b * LDROW + n + (n >> 3);
+    else return n * P + b;
+  }
+};
+
+template <typename S, int N, int PX, int PO, bool CONTIG, bool INV, class ORD, int s>
+__device__ __forceinline__ void compute_stage(double2 (&v)[Plan<N>::E], const double2* __restrict__ tw) {
+  using G = PassGeom<S, N, PX, PO, CONTIG>;
+  constexpr int r = ORD::r(s), p = ORD::p(s);
+  constexpr int E = G::E;
+#pragma unroll
+  for (int u = 0; u < E / r; ++u) {
+    int b, i;
+    G::template map<r>(threadIdx.x + G::WG * u, b, i);
+    double2* x = &v[u * r];
+    if constexpr (p > 1) {
+      const int k = i % p;
+      constexpr int step = N / (p * r);
+#pragma unroll
+      for (int m = 1; m < r; ++m) {
+        double2 w = tw[m * k * step];
+        if constexpr (INV) w.y = -w.y;
+        x[m] = cmul(x[m], w);
+      }
+    }
+    Bfly<r, INV>::run(x);
+  }
+}
+
+// Write the outputs of stage s-1 to LDS and read the inputs of stage s.
+template <typename S, int N, int PX, int PO, bool CONTIG, class ORD, int s>
+__device__ __forceinline__ void exchange(double2 (&v)[Plan<N>::E], double2* lds) {
+  using G = PassGeom<S, N, PX, PO, CONTIG>;
+  constexpr int r1 = ORD::r(s - 1), p1 = ORD::p(s - 1);
+  constexpr int r2 = ORD::r(s);
+  constexpr int E = G::E;
+#pragma unroll
+  for (int u = 0; u < E / r1; ++u) {
+    int b, i;
+    G::template map<r1>(threadIdx.x + G::WG * u, b, i);
+    const int k = i % p1;
+    const int j = (i - k) * r1 + k;
+#pragma unroll
+    for (int q = 0; q < r1; ++q) lds[G::lidx(b, j + q * p1)] = v[u * r1 + q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < E / r2; ++u) {
+    int b, i;
+    G::template map<r2>(threadIdx.x + G::WG * u, b, i);
+#pragma unroll
+    for (int m = 0; m < r2; ++m) v[u * r2 + m] = lds[G::lidx(b, i + m * (N / r2))];
+  }
+  __syncthreads();
+}
+
+// All stages of one transform direction; v holds the inputs of stage 0 on
+// entry and the outputs of the last stage on exit.
+template <typename S, int N, int PX, int PO, bool CONTIG, bool INV, bool REV>
+__device__ __forceinline__ void transform(double2 (&v)[Plan<N>::E], double2* lds, const double2* __restrict__ tw) {
+  using ORD = Order<Plan<N>, REV>;
+  constexpr int NS = Plan<N>::S;
+  static_assert(NS <= 5, "at most 5 stages");
+  compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 0>(v, tw);
+  if constexpr (NS > 1) {
+    exchange<S, N, PX, PO, CONTIG, ORD, 1>(v, lds);
+    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 1>(v, tw);
+  }
+  if constexpr (NS > 2) {
+    exchange<S, N, PX, PO, CONTIG, ORD, 2>(v, lds);
+    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 2>(v, tw);
+  }
+  if constexpr (NS > 3) {
+    exchange<S, N, PX, PO, CONTIG, ORD, 3>(v, lds);
+    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 3>(v, tw);
+  }
+  if constexpr (NS > 4) {
+    exchange<S, N, PX, PO, CONTIG, ORD, 4>(v, lds);
+    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 4>(v, tw);
+  }
+}
+
+// Pass kernel.  FUSED: transform (direction INV1) - mid op - transform
+// (opposite direction, reversed radix order).  Not FUSED: one transform in
+// direction INV1.
+template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1>
+__global__ void __launch_bounds__(PX * PO * N / Plan<N>::E)
+pass_kernel(PassArgs a) {
+  using G = PassGeom<S, N, PX, PO, CONTIG>;
+  using PL = Plan<N>;
+  constexpr int E = G::E, WG = G::WG, P = G::P;
+  constexpr int r_first = PL::R[0];                                // first stage of the first transform
+  constexpr int r_last = FUSED ? PL::R[0] : PL::R[PL::S - 1];      // last stage of the last transform
+  constexpr int NRED = CONTIG ? NRED_OBS : 1;
+
+  __shared__ double2 lds[G::LDS];
+  __shared__ double red[((WG + 63) / 64) * NRED_OBS];
+
+  const S* __restrict__ in = (const S*)a.in;
+  S* __restrict__ out = (S*)a.out;
+
+  // Tile origin.
+  const int t0 = blockIdx.x, t1 = blockIdx.y;
+  // pencil b -> (valid, base offset, pencil coordinates)
+  auto pencil = [&](int b, long long& base, int& c0, int& c1) -> bool {
+    if constexpr (CONTIG) {
+      const int y = t0 * P + b, z = t1;
+      c0 = y; c1 = z;
+      base = ((long long)z * a.ny + y) * a.nx;
+      return y < a.ny;
+    } else {
+      const int x = t0 * PX + (b % PX), o = t1 * PO + (b / PX);
+      c0 = x; c1 = o;
+      base = (long long)o * a.ostride + x;
+      return x < a.nx && o < a.nouter;
+    }
+  };
+  auto elem = [&](long long base, int n) -> long long {
+    if constexpr (CONTIG) return base + n;
+    else return base + (long long)n * a.nstride;
+  };
+
+  double acc[NRED_OBS];
+#pragma unroll
+  for (int q = 0; q < NRED_OBS; ++q) acc[q] = 0.0;
+
+  double2 v[E];
+  // ---- load (stage-0 inputs of the first transform) + pre ops ----
+#pragma unroll
+  for (int u = 0; u < E / r_first; ++u) {
+    int b, i;
+    G::template map<r_first>(threadIdx.x + WG * u, b, i);
+    long long base; int c0, c1;
+    const bool ok = pencil(b, base, c0, c1);
+#pragma unroll
+    for (int m = 0; m < r_first; ++m) {
+      const int n = i + m * (N / r_first);
+      double2 val = make_double2(0.0, 0.0);
+      if (ok) {
+        const long long e = elem(base, n);
+        val = ld2(in + e);
+        if constexpr (CONTIG) {
+          if (a.pre & PRE_ADJ) {
+            const double2 w = ld2((const S*)a.aux + e);
+            const double im = val.x * w.y - val.y * w.x;   // Im(conj(lambda) psi)
+            for (int j = 0; j < a.nguides; ++j)
+              acc[j] -= a.ctapD[((long long)j * a.nz + c1) * a.nx + n] * a.ctapB[(long long)j * a.ny + c0] * im;
+          }
+          if (a.pre & PRE_SCALE) val = cscale(val, *a.scale);
+          if (a.pre & PRE_VPHASE) val = cmul(val, phase_factor(potential_at(a, n, c0, c1) * a.cpre, a.imag));
+        }
+      }
+      v[u * r_first + m] = val;
+    }
+  }
+
+  transform<S, N, PX, PO, CONTIG, INV1, false>(v, lds, a.tw);
+
+  if constexpr (FUSED) {
+    // outputs of the last stage sit at n = i + q N / r, r = PL::R[S-1]
+    constexpr int rm = PL::R[PL::S - 1];
+#pragma unroll
+    for (int u = 0; u < E / rm; ++u) {
+      int b, i;
+      G::template map<rm>(threadIdx.x + WG * u, b, i);
+      long long base; int c0, c1;
+      pencil(b, base, c0, c1);
+#pragma unroll
+      for (int q = 0; q < rm; ++q) {
+        const int n = i + q * (N / rm);
+        double2& val = v[u * rm + q];
+        if constexpr (CONTIG) {
+          if (a.mid == MID_VPHASE) {
+            const int y = c0 < a.ny ? c0 : a.ny - 1;
+            val = cmul(val, phase_factor(potential_at(a, n, y, c1) * a.cmid, a.imag));
+          }
+        } else {
+          if (a.mid == MID_KINETIC) {
+            const int x = c0 < a.nx ? c0 : a.nx - 1, y = c1 < a.nouter ? c1 : a.nouter - 1;
+            val = cmul(val, cmul(cmul(a.kt[0][x], a.kt[1][y]), a.kt[2][n]));
+          }
+        }
+      }
+    }
+    transform<S, N, PX, PO, CONTIG, !INV1, true>(v, lds, a.tw);
+  }
+
+  // ---- post ops + store (outputs of the last stage at n = i + q N / r_last) ----
+#pragma unroll
+  for (int u = 0; u < E / r_last; ++u) {
+    int b, i;
+    G::template map<r_last>(threadIdx.x + WG * u, b, i);
+    long long base; int c0, c1;
+    const bool ok = pencil(b, base, c0, c1);
+#pragma unroll
+    for (int q = 0; q < r_last; ++q) {
+      const int n = i + q * (N / r_last);
+      double2 val = v[u * r_last + q];
+      if (ok) {
+        const long long e = elem(base, n);
+        if constexpr (CONTIG) {
+          double V = 0.0;
+          if (a.post & (POST_VPHASE | POST_OBS)) V = potential_at(a, n, c0, c1);
+          if (a.post & POST_VPHASE) val = cmul(val, phase_factor(V * a.cpost, a.imag));
+          const double2 sv = rounded(val, out);
+          if (a.post & POST_OBS) {
+            const double rho = sv.x * sv.x + sv.y * sv.y;
+            acc[0] += rho;
+            acc[1] += (a.lo[0] + n * a.d[0]) * rho;
+            acc[2] += (a.lo[1] + c0 * a.d[1]) * rho;
+            acc[3] += (a.lo[2] + c1 * a.d[2]) * rho;
+            if (n < a.ix_lo) acc[4] += rho;
+            else if (n > a.ix_hi) acc[6] += rho;
+            else acc[5] += rho;
+            acc[7] += V * rho;
+          }
+          if (a.post & POST_ADJ) {
+            const double2 w = ld2((const S*)a.aux + e);
+            const double im = sv.x * w.y - sv.y * w.x;
+            for (int j = 0; j < a.nguides; ++j)
+              acc[j] -= a.ctapD[((long long)j * a.nz + c1) * a.nx + n] * a.ctapB[(long long)j * a.ny + c0] * im;
+          }
+        } else {
+          if (a.post & POST_KIN) {
+            // z pencils of a field transformed along x and y: bins (c0, c1, n)
+            const int mx = 2 * c0 < a.nx ? c0 : c0 - a.nx;
+            const int my = 2 * c1 < a.ny ? c1 : c1 - a.ny;
+            const int mz = 2 * n < a.nz ? n : n - a.nz;
+            const double kx = a.kfac[0] * mx, ky = a.kfac[1] * my, kz = a.kfac[2] * mz;
+            acc[0] += 0.5 * (kx * kx + ky * ky + kz * kz) * (val.x * val.x + val.y * val.y);
+          }
+        }
+        st2(out + e, val);
+      }
+    }
+  }
+
+  if (a.post & (POST_OBS | POST_ADJ | POST_KIN) || (a.pre & PRE_ADJ)) {
+    double* dst = a.partials + (long long)(blockIdx.y * gridDim.x + blockIdx.x) * NRED_OBS;
+    block_sum<WG, NRED_OBS>(acc, dst, red);
+  }
+  (void)NRED;
+}
+
+// ---------------------------------------------------------------------------
+// Launcher for one (N, storage) pair.
+// ---------------------------------------------------------------------------
+template <typename S, int N, int DT>
+hipError_t launch_pass(int kind, const PassArgs& a, dim3 grid, hipStream_t st) {
+  constexpr int CR = Shape<N>::cr();
+  constexpr int SX = Shape<N>::sx(DT), SO = Shape<N>::so(DT);
+  switch (kind) {
+    case CONTIG_FWD:
+      hipLaunchKernelGGL((pass_kernel<S, N, CR, 1, true, false, false>), grid,
+                         dim3(PassGeom<S, N, CR, 1, true>::WG), 0, st, a);
+      break;
+    case CONTIG_INV:
+      hipLaunchKernelGGL((pass_kernel<S, N, CR, 1, true, false, true>), grid,
+                         dim3(PassGeom<S, N, CR, 1, true>::WG), 0, st, a);
+      break;
+    case CONTIG_FUSED:
+      hipLaunchKernelGGL((pass_kernel<S, N, CR, 1, true, true, true>), grid,
+                         dim3(PassGeom<S, N, CR, 1, true>::WG), 0, st, a);
+      break;
+    case STRIDED_FWD:
+      hipLaunchKernelGGL((pass_kernel<S, N, SX, SO, false, false, false>), grid,
+                         dim3(PassGeom<S, N, SX, SO, false>::WG), 0, st, a);
+      break;
+    case STRIDED_INV:
+      hipLaunchKernelGGL((pass_kernel<S, N, SX, SO, false, false, true>), grid,
+                         dim3(PassGeom<S, N, SX, SO, false>::WG), 0, st, a);
+      break;
+    case STRIDED_FUSED:
+      hipLaunchKernelGGL((pass_kernel<S, N, SX, SO, false, true, false>), grid,
+                         dim3(PassGeom<S, N, SX, SO, false>::WG), 0, st, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_any(int kind, int dt_index, const PassArgs& a, dim3 grid, hipStream_t st) {
+  return dt_index == 0 ? launch_pass<float2, N, 0>(kind, a, grid, st)
+                       : launch_pass<double2, N, 1>(kind, a, grid, st);
+}
+
+template <int N>
+constexpr KernelSet make_kernel_set() {
+  return KernelSet{
+      N,
+      {PassShape{Shape<N>::cr(), 1, PassGeom<float2, N, Shape<N>::cr(), 1, true>::WG},
+       PassShape{Shape<N>::cr(), 1, PassGeom<double2, N, Shape<N>::cr(), 1, true>::WG}},
+      {PassShape{Shape<N>::sx(0), Shape<N>::so(0), PassGeom<float2, N, Shape<N>::sx(0), Shape<N>::so(0), false>::WG},
+       PassShape{Shape<N>::sx(1), Shape<N>::so(1), PassGeom<double2, N, Shape<N>::sx(1), Shape<N>::so(1), false>::WG}},
+      &launch_any<N>};
+}
+
+}  // namespace ssf

@@ -1,0 +1,847 @@
+// Host runtime and C ABI of libssf (declarations and contracts: include/ssf.h).
+//
+// The runtime owns per-grid tables (FP64 twiddles, kinetic phase tables,
+// three-guide potential tables), the FP64 partial-sum workspace, and the
+// sequencing of pencil passes for one Strang step of the Fourier
+// split-operator method (Morgan et al., arXiv:1309.2451, Sec. IV):
+//   x forward (+ exp(-i V dt/2) on load) -> y forward -> z forward, kinetic
+//   phase, z inverse (one pass) -> y inverse -> x inverse (+ exp(-i V dt/2),
+//   + reductions on store).
+// Between two steps with no observation the x inverse / x forward pair is one
+// fused pass with exp(-i V dt) in the middle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ssf.h"
+#include "ssf_pass.hpp"
+
+using ssf::PassArgs;
+using ssf::KernelSet;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ssf_status fail(ssf_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      return fail(e_ == hipErrorOutOfMemory ? SSF_E_NOMEM : SSF_E_DEVICE,             \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    }                                                                                 \
+  } while (0)
+
+#define SSF_TRY(expr)                \
+  do {                               \
+    ssf_status s_ = (expr);          \
+    if (s_ != SSF_OK) return s_;     \
+  } while (0)
+
+const KernelSet* find_kernels(int n) {
+#define SSF_CASE(NN) \
+  if (n == NN) return &ssf::kernels_##NN;
+  SSF_LENGTHS(SSF_CASE)
+#undef SSF_CASE
+  return nullptr;
+}
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// Small kernels: tables, finalisation of reductions, pointwise helpers.
+// ---------------------------------------------------------------------------
+
+// Kinetic factor table of one axis: t[j] = exp(-i k_j^2 c) (or exp(-k_j^2 c)
+// in imaginary time) times `extra`, k_j = kfac * (j if 2j < n else j - n).
+// The phase argument is formed in FP64 from the integer m^2 and reduced
+// modulo 2 pi with a two-part constant before sincos.
+__global__ void ktab_kernel(double2* t, int n, double kfac, double c, int imag, double extra) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int m = 2 * j < n ? j : j - n;
+  const double k = kfac * (double)m;
+  const double th = k * k * c;
+  double2 f;
+  if (imag) {
+    f = make_double2(exp(-th) * extra, 0.0);
+  } else {
+    const double q = rint(th * 0.15915494309189533577);
+    double r = fma(-q, 6.283185307179586232, th);
+    r = fma(-q, 2.4492935982947064e-16, r);
+    double s, co;
+    sincos(r, &s, &co);
+    f = make_double2(co * extra, -s * extra);
+  }
+  t[j] = f;
+}
+
+// Sum NV partial vectors (stride 8) in a fixed order: thread t takes blocks
+// t, t+256, ...; then a fixed-shape tree.  Deterministic.
+template <int NV>
+__device__ void sum_partials(const double* p, long long nblk, double (&out)[NV], double* sh) {
+  double acc[NV];
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (long long b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (int q = 0; q < NV; ++q) acc[q] += p[b * 8 + q];
+  for (int q = 0; q < NV; ++q) sh[q * 256 + threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < NV; ++q) sh[q * 256 + threadIdx.x] += sh[q * 256 + threadIdx.x + w];
+    __syncthreads();
+  }
+  for (int q = 0; q < NV; ++q) out[q] = sh[q * 256];
+}
+
+// Finalise an observation from the x-pass partials.  mode bit 0: write obs;
+// bit 1: imaginary time (energy = -ln(norm)/(2 dtau), scale = 1/sqrt(norm)).
+// kin != nullptr: energy = sum kin * dv / npts + epot.
+__global__ void __launch_bounds__(256) obs_finalize(const double* partials, long long nblk, double dv,
+                                                    ssf_obs* obs, long long step, int mode, double dtau,
+                                                    double* scale, const double* kin, long long nkin,
+                                                    double npts) {
+  __shared__ double sh[8 * 256];
+  double s[8];
+  sum_partials<8>(partials, nblk, s, sh);
+  double ek = 0.0;
+  if (kin) {
+    __syncthreads();
+    double k1[1];
+    sum_partials<1>(kin, nkin, k1, sh);
+    ek = k1[0];
+  }
+  if (threadIdx.x != 0) return;
+  const double norm = s[0] * dv;
+  ssf_obs o;
+  o.norm = norm;
+  o.mean[0] = s[1] * dv;
+  o.mean[1] = s[2] * dv;
+  o.mean[2] = s[3] * dv;
+  o.pop[0] = s[4] * dv;
+  o.pop[1] = s[5] * dv;
+  o.pop[2] = s[6] * dv;
+  o.epot = s[7] * dv;
+  o.energy = 0.0;
+  if (mode & 2) o.energy = -log(norm) / (2.0 * dtau);
+  if (kin) o.energy = ek * dv / npts + o.epot;
+  o.step = step;
+  o.flags = isfinite(norm) ? 0 : 1;
+  o.reserved = 0;
+  if ((mode & 1) && obs) *obs = o;
+  if ((mode & 2) && scale) *scale = 1.0 / sqrt(norm);
+}
+
+// G[g][z] += w * sum over the y tiles of plane z of the x-pass partials.
+__global__ void adj_finalize(const double* partials, int ytiles, int nz, int nguides, double w, double* G) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nz * nguides) return;
+  const int g = t / nz, z = t % nz;
+  double s = 0.0;
+  for (int yt = 0; yt < ytiles; ++yt) s += partials[((long long)z * ytiles + yt) * 8 + g];
+  G[(long long)g * nz + z] += w * s;
+}
+
+// Norm, moments, populations and potential energy of a stored field, with the
+// same partial layout as the x pass: block (y tile of `rows` rows, plane z).
+template <typename S>
+__global__ void __launch_bounds__(256) obs_reduce_kernel(PassArgs a, int rows) {
+  __shared__ double red[4 * 8];
+  const int z = blockIdx.y, y0 = blockIdx.x * rows;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const S* in = (const S*)a.in;
+  for (int e = threadIdx.x; e < rows * a.nx; e += 256) {
+    const int y = y0 + e / a.nx, x = e % a.nx;
+    if (y >= a.ny) break;
+    const double2 v = ssf::ld2(in + ((long long)z * a.ny + y) * a.nx + x);
+    const double rho = v.x * v.x + v.y * v.y;
+    acc[0] += rho;
+    acc[1] += (a.lo[0] + x * a.d[0]) * rho;
+    acc[2] += (a.lo[1] + y * a.d[1]) * rho;
+    acc[3] += (a.lo[2] + z * a.d[2]) * rho;
+    if (x < a.ix_lo) acc[4] += rho;
+    else if (x > a.ix_hi) acc[6] += rho;
+    else acc[5] += rho;
+    acc[7] += ssf::potential_at(a, x, y, z) * rho;
+  }
+  ssf::block_sum<256, 8>(acc, a.partials + (long long)(blockIdx.y * gridDim.x + blockIdx.x) * 8, red);
+}
+
+template <typename S>
+__global__ void scale_kernel(S* p, long long n, const double* scale) {
+  const double s = *scale;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double2 v = ssf::ld2(p + i);
+    ssf::st2(p + i, make_double2(v.x * s, v.y * s));
+  }
+}
+
+// lambda = psi where x > x_hi (ix > ix_hi), 0 elsewhere.
+template <typename S>
+__global__ void mask_kernel(const S* psi, S* lam, long long n, int nx, int ix_hi) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx);
+    double2 v = ssf::ld2(psi + i);
+    if (x <= ix_hi) v = make_double2(0.0, 0.0);
+    ssf::st2(lam + i, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Handle.
+// ---------------------------------------------------------------------------
+struct KTab {
+  double dt = 0.0;
+  int imag = -1;
+  double2* t = nullptr;  // [nx | ny | nz]
+  unsigned long long use = 0;
+};
+
+}  // namespace
+
+struct ssf_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, d[3] = {1, 1, 1};
+  double dv = 1.0;
+  int dtype = SSF_C128;
+  int dti = 1;                         // 0 = complex64, 1 = complex128
+  size_t esize = 16;
+  long long npts = 1;
+  const KernelSet* ks[3] = {nullptr, nullptr, nullptr};
+  double2* tw[3] = {nullptr, nullptr, nullptr};
+  static constexpr int NKT = 8;
+  KTab kt[NKT];
+  unsigned long long kt_clock = 0;
+  int vkind = ssf::V_NONE;
+  const void* vtab = nullptr;
+  double* ctap = nullptr;              // A | D | B
+  int nguides = 0;
+  int ix_lo = -1, ix_hi = 1 << 30;     // default: everything in P2
+  int fuse = 1;
+  double* partials = nullptr;          // workspace: 2 regions of part_cap blocks x 8 doubles
+  long long part_cap = 0;
+  double* dscal = nullptr;             // device scalars: [0] scale
+  void* work = nullptr;                // field-sized workspace (lazy)
+  // optional per-pass timing: an event pair around every pass launch
+  int timing = 0;
+  std::vector<hipEvent_t> ev[ssf::NUM_PASS_KINDS];
+  size_t ev_used[ssf::NUM_PASS_KINDS] = {};
+};
+
+namespace {
+
+long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+// Grid of one pass kind over the handle's field.
+dim3 pass_grid(const ssf_handle* h, int axis) {
+  const KernelSet* ks = h->ks[axis];
+  if (axis == 0) {
+    const int rows = ks->contig[h->dti].px;
+    return dim3((unsigned)ceil_div(h->n[1], rows), (unsigned)h->n[2], 1);
+  }
+  const auto& sh = ks->strided[h->dti];
+  const int nouter = axis == 1 ? h->n[2] : h->n[1];
+  return dim3((unsigned)ceil_div(h->n[0], sh.px), (unsigned)ceil_div(nouter, sh.po), 1);
+}
+
+PassArgs base_args(const ssf_handle* h, const void* in, void* out, int axis) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.nx = h->n[0];
+  a.ny = h->n[1];
+  a.nz = h->n[2];
+  a.axis = axis;
+  if (axis == 1) {
+    a.nstride = h->n[0];
+    a.ostride = (long long)h->n[0] * h->n[1];
+    a.nouter = h->n[2];
+  } else if (axis == 2) {
+    a.nstride = (long long)h->n[0] * h->n[1];
+    a.ostride = h->n[0];
+    a.nouter = h->n[1];
+  }
+  a.tw = h->tw[axis];
+  a.vkind = h->vkind;
+  a.vtab = h->vtab;
+  if (h->ctap) {
+    const long long plane = (long long)h->nguides * h->n[2] * h->n[0];
+    a.ctapA = h->ctap;
+    a.ctapD = h->ctap + plane;
+    a.ctapB = h->ctap + 2 * plane;
+  }
+  a.nguides = h->nguides;
+  a.scale = h->dscal;
+  a.partials = h->partials;
+  for (int q = 0; q < 3; ++q) {
+    a.lo[q] = h->lo[q];
+    a.d[q] = h->d[q];
+    a.kfac[q] = TWO_PI / (h->hi[q] - h->lo[q]);
+  }
+  a.ix_lo = h->ix_lo;
+  a.ix_hi = h->ix_hi;
+  return a;
+}
+
+ssf_status launch(ssf_handle* h, int kind, int axis, const PassArgs& a) {
+  const dim3 g = pass_grid(h, axis);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    auto& pool = h->ev[kind];
+    size_t& used = h->ev_used[kind];
+    while (pool.size() < 2 * (used + 1)) {
+      hipEvent_t ev;
+      HIP_TRY(hipEventCreate(&ev));
+      pool.push_back(ev);
+    }
+    e0 = pool[2 * used];
+    e1 = pool[2 * used + 1];
+    ++used;
+    HIP_TRY(hipEventRecord(e0, h->stream));
+  }
+  hipError_t e = h->ks[axis]->launch(kind, h->dti, a, g, h->stream);
+  if (e != hipSuccess) return fail(SSF_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
+  if (h->timing) HIP_TRY(hipEventRecord(e1, h->stream));
+  return SSF_OK;
+}
+
+long long blocks_of(const ssf_handle* h, int axis) {
+  const dim3 g = pass_grid(h, axis);
+  return (long long)g.x * g.y;
+}
+
+ssf_status check_handle(ssf_handle* h) {
+  if (!h) return fail(SSF_E_INVALID, "null handle");
+  HIP_TRY(hipSetDevice(h->device));
+  return SSF_OK;
+}
+
+ssf_status check_field(const ssf_handle* h, const void* p, const char* what) {
+  if (!p) return fail(SSF_E_INVALID, std::string(what) + " is null");
+  if (((uintptr_t)p) % (h->esize / 2) != 0)
+    return fail(SSF_E_INVALID, std::string(what) + " is not aligned to the element size");
+  return SSF_OK;
+}
+
+// Kinetic tables for (dt, imag): built on the device once, then reused.
+ssf_status get_ktab(ssf_handle* h, double dt, int imag, const double2** out) {
+  for (auto& k : h->kt)
+    if (k.t && k.dt == dt && k.imag == imag) {
+      k.use = ++h->kt_clock;
+      *out = k.t;
+      return SSF_OK;
+    }
+  KTab* slot = &h->kt[0];
+  for (auto& k : h->kt) {
+    if (!k.t) { slot = &k; break; }
+    if (k.use < slot->use) slot = &k;
+  }
+  if (!slot->t) HIP_TRY(hipMalloc(&slot->t, sizeof(double2) * (h->n[0] + h->n[1] + h->n[2])));
+  double2* t = slot->t;
+  const double inv_n = 1.0 / (double)h->npts;
+  for (int a = 0; a < 3; ++a) {
+    const int n = h->n[a];
+    const double kfac = TWO_PI / (h->hi[a] - h->lo[a]);
+    hipLaunchKernelGGL(ktab_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, h->stream, t, n, kfac, 0.5 * dt,
+                       imag, a == 2 ? inv_n : 1.0);
+    HIP_TRY(hipGetLastError());
+    t += n;
+  }
+  slot->dt = dt;
+  slot->imag = imag;
+  slot->use = ++h->kt_clock;
+  *out = slot->t;
+  return SSF_OK;
+}
+
+ssf_status finalize_obs(ssf_handle* h, ssf_obs* obs, long long step, int mode, double dtau, const double* kin,
+                        long long nkin) {
+  hipLaunchKernelGGL(obs_finalize, dim3(1), dim3(256), 0, h->stream, h->partials, blocks_of(h, 0), h->dv, obs, step,
+                     mode, dtau, h->dscal, kin, nkin, (double)h->npts);
+  HIP_TRY(hipGetLastError());
+  return SSF_OK;
+}
+
+// Pointwise reduction of a stored field into the x-pass partial layout.
+ssf_status reduce_field(ssf_handle* h, const void* psi) {
+  PassArgs a = base_args(h, psi, nullptr, 0);
+  const int rows = h->ks[0]->contig[h->dti].px;
+  const dim3 g = pass_grid(h, 0);
+  if (h->dti == 0)
+    hipLaunchKernelGGL(obs_reduce_kernel<float2>, g, dim3(256), 0, h->stream, a, rows);
+  else
+    hipLaunchKernelGGL(obs_reduce_kernel<double2>, g, dim3(256), 0, h->stream, a, rows);
+  HIP_TRY(hipGetLastError());
+  return SSF_OK;
+}
+
+ssf_status scale_field(ssf_handle* h, void* psi) {
+  const unsigned blocks = (unsigned)std::min<long long>(ceil_div(h->npts, 256), 65536);
+  if (h->dti == 0)
+    hipLaunchKernelGGL(scale_kernel<float2>, dim3(blocks), dim3(256), 0, h->stream, (float2*)psi, h->npts, h->dscal);
+  else
+    hipLaunchKernelGGL(scale_kernel<double2>, dim3(blocks), dim3(256), 0, h->stream, (double2*)psi, h->npts, h->dscal);
+  HIP_TRY(hipGetLastError());
+  return SSF_OK;
+}
+
+// Middle of a step: y forward, z forward + kinetic + z inverse, y inverse.
+ssf_status step_middle(ssf_handle* h, void* psi, const double2* kt) {
+  PassArgs ay = base_args(h, psi, psi, 1);
+  SSF_TRY(launch(h, ssf::STRIDED_FWD, 1, ay));
+  PassArgs az = base_args(h, psi, psi, 2);
+  az.mid = ssf::MID_KINETIC;
+  az.kt[0] = kt;
+  az.kt[1] = kt + h->n[0];
+  az.kt[2] = kt + h->n[0] + h->n[1];
+  SSF_TRY(launch(h, ssf::STRIDED_FUSED, 2, az));
+  SSF_TRY(launch(h, ssf::STRIDED_INV, 1, ay));
+  return SSF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t ssf_supported_length(int32_t n) { return find_kernels(n) != nullptr ? 1 : 0; }
+
+const char* ssf_status_string(ssf_status s) {
+  switch (s) {
+    case SSF_OK: return "ok";
+    case SSF_E_INVALID: return "invalid argument";
+    case SSF_E_UNSUPPORTED: return "unsupported transform length";
+    case SSF_E_NOMEM: return "out of device memory";
+    case SSF_E_NODEVICE: return "no HIP device";
+    case SSF_E_DEVICE: return "HIP runtime error";
+    case SSF_E_NONFINITE: return "non-finite norm observed";
+    default: return "unknown status";
+  }
+}
+
+const char* ssf_last_error(void) { return g_last_error.c_str(); }
+
+ssf_status ssf_destroy(ssf_handle* h);
+
+ssf_status ssf_create(const ssf_grid_desc* grid, int32_t dtype, void* hip_stream, ssf_handle** out) {
+  if (!grid || !out) return fail(SSF_E_INVALID, "null argument");
+  *out = nullptr;
+  if (dtype != SSF_C64 && dtype != SSF_C128) return fail(SSF_E_INVALID, "dtype must be SSF_C64 or SSF_C128");
+  for (int a = 0; a < 3; ++a) {
+    if (grid->n[a] < 1) return fail(SSF_E_INVALID, "grid sizes must be >= 1");
+    if (!(grid->hi[a] > grid->lo[a]) || !std::isfinite(grid->hi[a] - grid->lo[a]))
+      return fail(SSF_E_INVALID, "grid needs hi > lo on every axis");
+    if (!find_kernels(grid->n[a]))
+      return fail(SSF_E_UNSUPPORTED, "transform length " + std::to_string(grid->n[a]) + " is not supported");
+  }
+  if ((long long)grid->n[1] > 0 && grid->n[2] > 65535) return fail(SSF_E_INVALID, "Nz must be <= 65535");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(SSF_E_NODEVICE, "no HIP device visible");
+  ssf_handle* h = new ssf_handle();
+  HIP_TRY(hipGetDevice(&h->device));
+  h->stream = (hipStream_t)hip_stream;
+  h->dtype = dtype;
+  h->dti = dtype == SSF_C64 ? 0 : 1;
+  h->esize = dtype == SSF_C64 ? 8 : 16;
+  h->npts = 1;
+  for (int a = 0; a < 3; ++a) {
+    h->n[a] = grid->n[a];
+    h->lo[a] = grid->lo[a];
+    h->hi[a] = grid->hi[a];
+    h->d[a] = (grid->hi[a] - grid->lo[a]) / grid->n[a];
+    h->npts *= grid->n[a];
+    h->ks[a] = find_kernels(grid->n[a]);
+  }
+  h->dv = h->d[0] * h->d[1] * h->d[2];
+  auto cleanup = [&](ssf_status s) { ssf_destroy(h); return s; };
+  // twiddles W_N[t] = exp(-2 pi i t / N), each from its own cos/sin in FP64
+  for (int a = 0; a < 3; ++a) {
+    const int n = h->n[a];
+    std::vector<double2> w(n);
+    for (int t = 0; t < n; ++t) {
+      const double ang = TWO_PI * (double)t / (double)n;
+      w[t] = make_double2(std::cos(ang), -std::sin(ang));
+    }
+    if (hipMalloc(&h->tw[a], sizeof(double2) * n) != hipSuccess) return cleanup(fail(SSF_E_NOMEM, "twiddle table"));
+    if (hipMemcpy(h->tw[a], w.data(), sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(SSF_E_DEVICE, "twiddle upload"));
+  }
+  long long cap = 0;
+  for (int a = 0; a < 3; ++a) cap = std::max(cap, blocks_of(h, a));
+  h->part_cap = cap;
+  if (hipMalloc(&h->partials, sizeof(double) * 8 * cap * 2) != hipSuccess)
+    return cleanup(fail(SSF_E_NOMEM, "partials workspace"));
+  if (hipMalloc(&h->dscal, sizeof(double) * 8) != hipSuccess) return cleanup(fail(SSF_E_NOMEM, "device scalars"));
+  const double one[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+  if (hipMemcpy(h->dscal, one, sizeof(one), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(SSF_E_DEVICE, "device scalars upload"));
+  *out = h;
+  return SSF_OK;
+}
+
+ssf_status ssf_destroy(ssf_handle* h) {
+  if (!h) return SSF_OK;
+  (void)hipSetDevice(h->device);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  for (auto& k : h->kt) if (k.t) (void)hipFree(k.t);
+  for (int a = 0; a < 3; ++a) if (h->tw[a]) (void)hipFree(h->tw[a]);
+  if (h->ctap) (void)hipFree(h->ctap);
+  if (h->partials) (void)hipFree(h->partials);
+  if (h->dscal) (void)hipFree(h->dscal);
+  if (h->work) (void)hipFree(h->work);
+  for (auto& pool : h->ev)
+    for (hipEvent_t ev : pool) (void)hipEventDestroy(ev);
+  delete h;
+  if (e != hipSuccess) return fail(SSF_E_DEVICE, std::string("stream error at destroy: ") + hipGetErrorString(e));
+  return SSF_OK;
+}
+
+ssf_status ssf_set_stream(ssf_handle* h, void* hip_stream) {
+  SSF_TRY(check_handle(h));
+  h->stream = (hipStream_t)hip_stream;
+  return SSF_OK;
+}
+
+ssf_status ssf_set_timing(ssf_handle* h, int32_t on) {
+  SSF_TRY(check_handle(h));
+  h->timing = on ? 1 : 0;
+  for (auto& u : h->ev_used) u = 0;
+  return SSF_OK;
+}
+
+ssf_status ssf_timing_read(ssf_handle* h, double* ms_total, int64_t* launches) {
+  SSF_TRY(check_handle(h));
+  if (!ms_total || !launches) return fail(SSF_E_INVALID, "null output arrays");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int k = 0; k < ssf::NUM_PASS_KINDS; ++k) {
+    double tot = 0.0;
+    for (size_t i = 0; i < h->ev_used[k]; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev[k][2 * i], h->ev[k][2 * i + 1]));
+      tot += ms;
+    }
+    ms_total[k] = tot;
+    launches[k] = (int64_t)h->ev_used[k];
+    h->ev_used[k] = 0;
+  }
+  return SSF_OK;
+}
+
+ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps) {
+  SSF_TRY(check_handle(h));
+  h->fuse = fuse_steps ? 1 : 0;
+  return SSF_OK;
+}
+
+ssf_status ssf_set_potential_table(ssf_handle* h, const void* v_dev, int32_t v_is_f64) {
+  SSF_TRY(check_handle(h));
+  if (!v_dev) return fail(SSF_E_INVALID, "potential table is null");
+  h->vkind = v_is_f64 ? ssf::V_TAB64 : ssf::V_TAB32;
+  h->vtab = v_dev;
+  return SSF_OK;
+}
+
+ssf_status ssf_clear_potential(ssf_handle* h) {
+  SSF_TRY(check_handle(h));
+  h->vkind = ssf::V_NONE;
+  h->vtab = nullptr;
+  return SSF_OK;
+}
+
+ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d) {
+  SSF_TRY(check_handle(h));
+  if (!d || !d->xc) return fail(SSF_E_INVALID, "null guide description");
+  if (d->nguides < 1 || d->nguides > ssf::MAX_GUIDES) return fail(SSF_E_INVALID, "nguides must be 1..3");
+  for (int g = 0; g < d->nguides; ++g)
+    if (!(d->sigma[g] > 0.0) || !std::isfinite(d->v0[g])) return fail(SSF_E_INVALID, "sigma must be > 0, v0 finite");
+  const int nx = h->n[0], ny = h->n[1], nz = h->n[2], ng = d->nguides;
+  const long long plane = (long long)ng * nz * nx;
+  std::vector<double> tab(2 * plane + (long long)ng * ny);
+  for (int g = 0; g < ng; ++g) {
+    const double s2 = d->sigma[g] * d->sigma[g];
+    for (int z = 0; z < nz; ++z) {
+      const double xc = d->xc[(long long)g * nz + z];
+      for (int x = 0; x < nx; ++x) {
+        const double dx = h->lo[0] + x * h->d[0] - xc;
+        const double A = d->v0[g] * std::exp(-dx * dx / (2.0 * s2));
+        tab[((long long)g * nz + z) * nx + x] = A;
+        tab[plane + ((long long)g * nz + z) * nx + x] = A * dx / s2;
+      }
+    }
+    for (int y = 0; y < ny; ++y) {
+      const double yc = h->lo[1] + y * h->d[1];
+      tab[2 * plane + (long long)g * ny + y] = std::exp(-yc * yc / (2.0 * s2));
+    }
+  }
+  if (h->ctap) { HIP_TRY(hipStreamSynchronize(h->stream)); (void)hipFree(h->ctap); h->ctap = nullptr; }
+  HIP_TRY(hipMalloc(&h->ctap, sizeof(double) * tab.size()));
+  HIP_TRY(hipMemcpy(h->ctap, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+  h->nguides = ng;
+  h->vkind = ssf::V_CTAP;
+  h->vtab = nullptr;
+  return SSF_OK;
+}
+
+ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi) {
+  SSF_TRY(check_handle(h));
+  if (!(x_lo <= x_hi)) return fail(SSF_E_INVALID, "partition needs x_lo <= x_hi");
+  // P1: x_i < x_lo, P3: x_i > x_hi with x_i = lo + i d (same FP64 expression as the coordinates)
+  int ilo = 0, ihi = h->n[0] - 1;
+  ilo = 0;
+  while (ilo < h->n[0] && h->lo[0] + ilo * h->d[0] < x_lo) ++ilo;   // first index not in P1
+  ihi = h->n[0] - 1;
+  while (ihi >= 0 && h->lo[0] + ihi * h->d[0] > x_hi) --ihi;        // last index not in P3
+  h->ix_lo = ilo;
+  h->ix_hi = ihi;
+  return SSF_OK;
+}
+
+ssf_status ssf_fft(ssf_handle* h, void* psi, int32_t axis_mask, int32_t inverse) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi, "psi"));
+  for (int a = 0; a < 3; ++a) {
+    if (!(axis_mask & (1 << a))) continue;
+    PassArgs pa = base_args(h, psi, psi, a);
+    const int kind = a == 0 ? (inverse ? ssf::CONTIG_INV : ssf::CONTIG_FWD)
+                            : (inverse ? ssf::STRIDED_INV : ssf::STRIDED_FWD);
+    SSF_TRY(launch(h, kind, a, pa));
+  }
+  return SSF_OK;
+}
+
+static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t nsteps, double dt, int imag,
+                            int64_t obs_every, ssf_obs* obs_dev, bool allow_fuse) {
+  const double2* kt = nullptr;
+  SSF_TRY(get_ktab(h, dt, imag, &kt));
+  if (imag) {
+    // scale the input to norm 1 first
+    SSF_TRY(reduce_field(h, src));
+    SSF_TRY(finalize_obs(h, nullptr, 0, 2, dt, nullptr, 0));
+  }
+  const bool fuse = allow_fuse && h->fuse && !imag;
+  int64_t s = 0;
+  const void* cur_in = src;
+  while (s < nsteps) {
+    // chain start: x forward with exp(-i V dt/2) on load
+    PassArgs ax = base_args(h, cur_in, psi, 0);
+    ax.pre = ssf::PRE_VPHASE | (imag ? ssf::PRE_SCALE : 0);
+    ax.cpre = 0.5 * dt;
+    ax.imag = imag;
+    SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
+    cur_in = psi;
+    for (;;) {
+      SSF_TRY(step_middle(h, psi, kt));
+      ++s;
+      const bool obs_due = obs_every > 0 && obs_dev && (s % obs_every) == 0;
+      const bool end = !fuse || s == nsteps || obs_due;
+      if (end) {
+        PassArgs ai = base_args(h, psi, psi, 0);
+        ai.post = ssf::POST_VPHASE | ((obs_due || imag) ? ssf::POST_OBS : 0);
+        ai.cpost = 0.5 * dt;
+        ai.imag = imag;
+        SSF_TRY(launch(h, ssf::CONTIG_INV, 0, ai));
+        if (obs_due || imag) {
+          ssf_obs* slot = obs_due ? obs_dev + (s / obs_every - 1) : nullptr;
+          SSF_TRY(finalize_obs(h, slot, s, (obs_due ? 1 : 0) | (imag ? 2 : 0), dt, nullptr, 0));
+        }
+        break;
+      }
+      PassArgs am = base_args(h, psi, psi, 0);
+      am.mid = ssf::MID_VPHASE;
+      am.cmid = dt;
+      am.imag = imag;
+      SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
+    }
+  }
+  if (imag && nsteps > 0) SSF_TRY(scale_field(h, psi));
+  return SSF_OK;
+}
+
+ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time, int64_t obs_every,
+                    ssf_obs* obs_dev) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi, "psi"));
+  if (nsteps < 0) return fail(SSF_E_INVALID, "nsteps must be >= 0");
+  if (time != SSF_REAL && time != SSF_IMAG) return fail(SSF_E_INVALID, "time must be SSF_REAL or SSF_IMAG");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
+  if (time == SSF_IMAG && dt < 0.0) return fail(SSF_E_INVALID, "imaginary time needs dt > 0");
+  if (obs_every < 0) return fail(SSF_E_INVALID, "obs_every must be >= 0");
+  if (nsteps == 0) return SSF_OK;
+  return run_steps(h, psi, psi, nsteps, dt, time == SSF_IMAG ? 1 : 0, obs_every, obs_dev, true);
+}
+
+ssf_status ssf_observables(ssf_handle* h, const void* psi, ssf_obs* obs_dev) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi, "psi"));
+  if (!obs_dev) return fail(SSF_E_INVALID, "obs_dev is null");
+  if (!h->work) HIP_TRY(hipMalloc(&h->work, h->esize * h->npts));
+  HIP_TRY(hipMemcpyAsync(h->work, psi, h->esize * h->npts, hipMemcpyDeviceToDevice, h->stream));
+  // kinetic part into the second partial region
+  double* kin = h->partials + 8 * h->part_cap;
+  PassArgs ax = base_args(h, h->work, h->work, 0);
+  SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
+  PassArgs ay = base_args(h, h->work, h->work, 1);
+  SSF_TRY(launch(h, ssf::STRIDED_FWD, 1, ay));
+  PassArgs az = base_args(h, h->work, h->work, 2);
+  az.post = ssf::POST_KIN;
+  az.partials = kin;
+  SSF_TRY(launch(h, ssf::STRIDED_FWD, 2, az));
+  SSF_TRY(reduce_field(h, psi));
+  return finalize_obs(h, obs_dev, 0, 1, 0.0, kin, blocks_of(h, 2));
+}
+
+ssf_status ssf_obs_read(ssf_handle* h, const ssf_obs* obs_dev, ssf_obs* host, int64_t count) {
+  SSF_TRY(check_handle(h));
+  if (count < 0 || (count > 0 && (!obs_dev || !host))) return fail(SSF_E_INVALID, "bad observation buffers");
+  if (count == 0) return SSF_OK;
+  HIP_TRY(hipMemcpyAsync(host, obs_dev, sizeof(ssf_obs) * count, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int64_t i = 0; i < count; ++i)
+    if (host[i].flags & 1) return fail(SSF_E_NONFINITE, "observation " + std::to_string(i) + " has a non-finite norm");
+  return SSF_OK;
+}
+
+ssf_status ssf_sync(ssf_handle* h) {
+  SSF_TRY(check_handle(h));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return SSF_OK;
+}
+
+ssf_status ssf_step_ckpt(ssf_handle* h, void* psi, int64_t nsteps, double dt, int64_t every, void* ckpt_dev) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi, "psi"));
+  SSF_TRY(check_field(h, ckpt_dev, "ckpt_dev"));
+  if (nsteps < 0 || every < 1) return fail(SSF_E_INVALID, "need nsteps >= 0 and every >= 1");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
+  const size_t fb = h->esize * h->npts;
+  for (int64_t s = 0, slot = 0; s < nsteps; s += every, ++slot) {
+    HIP_TRY(hipMemcpyAsync((char*)ckpt_dev + slot * fb, psi, fb, hipMemcpyDeviceToDevice, h->stream));
+    SSF_TRY(run_steps(h, psi, psi, std::min<int64_t>(every, nsteps - s), dt, 0, 0, nullptr, false));
+  }
+  return SSF_OK;
+}
+
+ssf_status ssf_step_seq(ssf_handle* h, const void* psi0, int64_t nsteps, double dt, void* seq_dev) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi0, "psi0"));
+  SSF_TRY(check_field(h, seq_dev, "seq_dev"));
+  if (nsteps < 0) return fail(SSF_E_INVALID, "nsteps must be >= 0");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
+  const size_t fb = h->esize * h->npts;
+  char* seq = (char*)seq_dev;
+  HIP_TRY(hipMemcpyAsync(seq, psi0, fb, hipMemcpyDeviceToDevice, h->stream));
+  for (int64_t s = 0; s < nsteps; ++s)
+    SSF_TRY(run_steps(h, seq + s * fb, seq + (s + 1) * fb, 1, dt, 0, 0, nullptr, false));
+  return SSF_OK;
+}
+
+ssf_status ssf_adjoint_init(ssf_handle* h, const void* psi, void* lambda) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi, "psi"));
+  SSF_TRY(check_field(h, lambda, "lambda"));
+  const unsigned blocks = (unsigned)std::min<long long>(ceil_div(h->npts, 256), 65536);
+  if (h->dti == 0)
+    hipLaunchKernelGGL(mask_kernel<float2>, dim3(blocks), dim3(256), 0, h->stream, (const float2*)psi, (float2*)lambda,
+                       h->npts, h->n[0], h->ix_hi);
+  else
+    hipLaunchKernelGGL(mask_kernel<double2>, dim3(blocks), dim3(256), 0, h->stream, (const double2*)psi,
+                       (double2*)lambda, h->npts, h->n[0], h->ix_hi);
+  HIP_TRY(hipGetLastError());
+  return SSF_OK;
+}
+
+ssf_status ssf_adjoint_segment(ssf_handle* h, void* lambda, const void* seq_dev, int64_t nsteps, double dt,
+                               double* G_dev) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, lambda, "lambda"));
+  SSF_TRY(check_field(h, seq_dev, "seq_dev"));
+  if (!G_dev) return fail(SSF_E_INVALID, "G_dev is null");
+  if (h->vkind != ssf::V_CTAP) return fail(SSF_E_INVALID, "the adjoint needs the guide potential (ssf_set_potential_ctap)");
+  if (nsteps < 0) return fail(SSF_E_INVALID, "nsteps must be >= 0");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
+  const double2* kt = nullptr;
+  SSF_TRY(get_ktab(h, -dt, 0, &kt));
+  const size_t fb = h->esize * h->npts;
+  const char* seq = (const char*)seq_dev;
+  const dim3 gx = pass_grid(h, 0);
+  const double w = dt * h->dv;
+  const int nzg = h->n[2] * h->nguides;
+  for (int64_t s = nsteps - 1; s >= 0; --s) {
+    // second potential half-step of step s: Im(conj(lambda_{s+1}) psi_{s+1}) on load, then A^dagger
+    PassArgs ax = base_args(h, lambda, lambda, 0);
+    ax.pre = ssf::PRE_ADJ | ssf::PRE_VPHASE;
+    ax.cpre = -0.5 * dt;
+    ax.aux = seq + (s + 1) * fb;
+    SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
+    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(nzg, 256)), dim3(256), 0, h->stream, h->partials,
+                       (int)gx.x, h->n[2], h->nguides, w, G_dev);
+    HIP_TRY(hipGetLastError());
+    SSF_TRY(step_middle(h, lambda, kt));
+    // first potential half-step of step s: A^dagger, then Im(conj(lambda_s) psi_s) on store
+    PassArgs ai = base_args(h, lambda, lambda, 0);
+    ai.post = ssf::POST_VPHASE | ssf::POST_ADJ;
+    ai.cpost = -0.5 * dt;
+    ai.aux = seq + s * fb;
+    SSF_TRY(launch(h, ssf::CONTIG_INV, 0, ai));
+    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(nzg, 256)), dim3(256), 0, h->stream, h->partials,
+                       (int)gx.x, h->n[2], h->nguides, w, G_dev);
+    HIP_TRY(hipGetLastError());
+  }
+  return SSF_OK;
+}
+
+ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int32_t nz, double* B_out) {
+  if (M < 4 || !(b > a) || nz < 0 || (nz > 0 && (!z || !B_out))) return fail(SSF_E_INVALID, "bad B-spline arguments");
+  const int nk = M + 4, nseg = M - 3;
+  std::vector<double> t(nk), N0(nk);
+  for (int i = 0; i < 4; ++i) { t[i] = a; t[nk - 1 - i] = b; }
+  for (int i = 1; i < nseg; ++i) t[3 + i] = a + (b - a) * (double)i / (double)nseg;
+  for (int iz = 0; iz < nz; ++iz) {
+    const double u = z[iz];
+    double* row = B_out + (long long)iz * M;
+    if (u >= b) {
+      for (int m = 0; m < M; ++m) row[m] = m == M - 1 ? 1.0 : 0.0;
+      continue;
+    }
+    // locate the knot span, then the de Boor triangle of the 4 nonzero functions
+    int span = 3;
+    while (span < M - 1 && u >= t[span + 1]) ++span;
+    double Nl[4] = {1.0, 0.0, 0.0, 0.0};
+    double left[4], right[4];
+    for (int d = 1; d <= 3; ++d) {
+      left[d] = u - t[span + 1 - d];
+      right[d] = t[span + d] - u;
+      double saved = 0.0;
+      for (int r = 0; r < d; ++r) {
+        const double den = right[r + 1] + left[d - r];
+        const double tmp = den > 0.0 ? Nl[r] / den : 0.0;
+        Nl[r] = saved + right[r + 1] * tmp;
+        saved = left[d - r] * tmp;
+      }
+      Nl[d] = saved;
+    }
+    for (int m = 0; m < M; ++m) row[m] = 0.0;
+    for (int r = 0; r < 4; ++r) {
+      const int m = span - 3 + r;
+      if (m >= 0 && m < M) row[m] = Nl[r];
+    }
+  }
+  return SSF_OK;
+}
+
+}  // extern "C"

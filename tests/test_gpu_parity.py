@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative L2 unless stated):
+  complex128 storage: 1e-12 (FP64 rounding of a few hundred passes);
+  complex64 storage: the input and every pass output are rounded to FP32
+  (unit roundoff 6e-8), arithmetic is FP64, so after n passes the error is a
+  random walk of at most ~6e-8 sqrt(n) per value; the bounds below allow 3x.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+ssf = pytest.importorskip("paper_1309_2451_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def to_dev(a, solver):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(solver.tdtype).to(DEV).contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def c64_round(a):
+    return np.asarray(a, dtype=np.complex64).astype(np.complex128)
+
+
+FFT_SHAPES = [(8, 8, 8), (12, 20, 40), (16, 32, 64), (1, 24, 160), (96, 48, 1), (4, 12, 512), (2, 4, 1024),
+              (20, 12, 96), (20, 2, 256), (12, 128, 8), (192, 1, 16), (2, 384, 20), (768, 2, 1), (80, 320, 2),
+              (4, 2, 640), (1, 1, 1)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", FFT_SHAPES)
+def test_fft_each_axis_vs_oracle(dtype, shape):
+    nz, ny, nx = shape
+    say("fft", dtype, shape)
+    s = ssf.Solver((nx, ny, nz), (0, 0, 0), (1, 1, 1), dtype)
+    rng = np.random.default_rng(nx * 7 + ny * 3 + nz)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    if dtype == "c64":
+        x = c64_round(x)
+    tol = 1e-13 if dtype == "c128" else 2e-7
+    for axis in range(3):
+        for inverse in (False, True):
+            t = to_dev(x, s)
+            s.fft(t, axes=(axis,), inverse=inverse)
+            ref = oracle.fft_axis(x, axis, +1 if inverse else -1)
+            assert rel(host(t), ref) < tol, (axis, inverse)
+    t = to_dev(x, s)
+    s.fft(t)
+    assert rel(host(t), oracle.fft3d(x, -1)) < tol * 2
+    s.close()
+
+
+def _random_case(shape, seed, vscale=10.0):
+    nz, ny, nx = shape
+    g = synth.Grid((nx, ny, nz), (-4.0, -3.0, -5.0), (4.0, 3.0, 5.0))
+    rng = np.random.default_rng(seed)
+    psi = synth.random_field(g, seed, smooth=2.0)
+    V = rng.uniform(-vscale, vscale, g.shape)
+    return g, psi, V
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("shape", [(20, 12, 40), (16, 24, 32), (12, 8, 96)])
+def test_step_random_c128_vs_oracle(shape, fuse):
+    say("step c128", shape, "fuse", fuse)
+    g, psi0, V = _random_case(shape, 5)
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128")
+    s.set_fusion(fuse)
+    Vt = torch.from_numpy(V).to(DEV)
+    s.set_potential_table(Vt)
+    s.set_partition(-1.0, 0.5)
+    t = to_dev(psi0, s)
+    dt, n = 0.013, 37
+    obs = s.step(t, n, dt, obs_every=5)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, dt, n)
+    assert rel(host(t), ref) < 1e-12
+    # observations at steps 5, 10, ..., 35
+    ref_psi = psi0
+    for k in range(len(obs)):
+        ref_psi, _ = oracle.step(ref_psi, V, g.lo, g.hi, dt, 5)
+        o = oracle.observables(ref_psi, V, g.lo, g.hi, -1.0, 0.5)
+        assert obs[k]["step"] == 5 * (k + 1)
+        assert abs(obs[k]["norm"] - o["norm"]) < 1e-12
+        for a, key in enumerate(("mx", "my", "mz")):
+            assert abs(obs[k]["mean"][a] - o[key]) < 1e-12
+        for a, key in enumerate(("p1", "p2", "p3")):
+            assert abs(obs[k]["pop"][a] - o[key]) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("shape", [(20, 12, 40), (12, 8, 96)])
+def test_step_random_c64_vs_oracle(shape):
+    say("step c64", shape)
+    g, psi0, V = _random_case(shape, 6)
+    psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    t = to_dev(psi0, s)
+    dt, n = 0.013, 50
+    s.step(t, n, dt)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, dt, n)
+    # 50 steps x 4-5 rounded passes
+    assert rel(host(t), ref) < 3 * 6e-8 * np.sqrt(50 * 5)
+    # float32 potential table: V itself is rounded, still close
+    s.set_potential_table(torch.from_numpy(V.astype(np.float32)).to(DEV))
+    t = to_dev(psi0, s)
+    s.step(t, n, dt)
+    ref32, _ = oracle.step(psi0, V.astype(np.float32).astype(np.float64), g.lo, g.hi, dt, n)
+    assert rel(host(t), ref32) < 3 * 6e-8 * np.sqrt(50 * 5)
+    s.close()
+
+
+def test_config1_harmonic_c128():
+    c = synth.config1()
+    g = c["grid"]
+    say("config1 harmonic 64^3 c128, 200 steps")
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128")
+    s.set_potential_table(torch.from_numpy(c["V"]).to(DEV))
+    s.set_partition(-1.5, 1.5)
+    t = to_dev(c["psi0"], s)
+    obs = s.step(t, c["steps"], c["dt"], obs_every=1)
+    ref, _ = oracle.step(c["psi0"], c["V"], g.lo, g.hi, c["dt"], c["steps"])
+    assert rel(host(t), ref) < 1e-12
+    theta = np.arccos(1.0 - c["dt"] ** 2 / 2.0)
+    n = np.arange(1, c["steps"] + 1)
+    assert np.max(np.abs(obs["mean"][:, 0] - np.cos(n * theta))) < 1e-11
+    assert np.max(np.abs(obs["norm"] - 1.0)) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_imaginary_time_vs_oracle(dtype):
+    say("imag", dtype)
+    g = synth.Grid((32, 24, 40), (-6.0, -5.0, -7.0), (6.0, 5.0, 7.0))
+    V = synth.harmonic_table(g, (1.0, 1.3, 0.8))
+    psi0 = synth.gaussian_packet(g, centre=(0.3, -0.2, 0.5), width=(1.3, 0.7, 1.1))
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    t = to_dev(psi0, s)
+    dtau, n = 0.01, 60
+    obs = s.step(t, n, dtau, imag=True, obs_every=1)
+    ref, ed = oracle.step(psi0, V, g.lo, g.hi, dtau, n, imag=True)
+    tol = 1e-12 if dtype == "c128" else 3 * 6e-8 * np.sqrt(5 * n)
+    assert rel(host(t), ref) < tol
+    assert np.max(np.abs(obs["energy"] - ed)) < (1e-9 if dtype == "c128" else 1e-3)
+    assert abs(obs["norm"][-1] - np.exp(-2 * ed[-1] * dtau)) < (1e-12 if dtype == "c128" else 1e-6)
+    o = s.observables(t)
+    assert abs(o["norm"] - 1.0) < (1e-13 if dtype == "c128" else 1e-6)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_observables_energy_vs_oracle(dtype):
+    say("observables", dtype)
+    g = synth.Grid((40, 24, 32), (-6.0, -5.0, -7.0), (6.0, 5.0, 7.0))
+    V = synth.harmonic_table(g, (1.0, 1.3, 0.8))
+    psi = synth.gaussian_packet(g, centre=(0.5, 0.2, -0.4), width=(0.9, 0.8, 1.2), k=(0.7, 0.0, -0.3))
+    if dtype == "c64":
+        psi = c64_round(psi)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    s.set_partition(-0.5, 1.0)
+    o = s.observables(to_dev(psi, s))
+    r = oracle.observables(psi, V, g.lo, g.hi, -0.5, 1.0)
+    tol = 1e-12
+    assert abs(o["norm"] - r["norm"]) < tol
+    # complex64: the kinetic part is summed from a transform whose passes round to FP32
+    assert abs(o["energy"] - r["energy"]) < (1e-11 if dtype == "c128" else 1e-7 * abs(r["energy"]))
+    assert abs(o["pop"][0] - r["p1"]) < tol and abs(o["pop"][2] - r["p3"]) < tol
+    s.close()
+
+
+def _ctap_small():
+    g = synth.Grid((32, 24, 64), (-5.0, -4.0, -16.0), (5.0, 4.0, 16.0))
+    guides = synth.ctap_guides(g, d0=2.0, delta=0.6, v0=12.0, sigma=0.6, z1=2.0, z3=-2.0, wg=3.0)
+    psi0 = synth.gaussian_packet(g, centre=(-2.0, 0.0, -6.0), width=(0.5, 0.5, 2.0), k=(0.0, 0.0, 2.0))
+    return g, guides, psi0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_guide_potential_step_vs_oracle(dtype):
+    say("ctap step", dtype)
+    g, gd, psi0 = _ctap_small()
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_guides(gd.v0, gd.sigma, gd.xc)
+    s.set_partition(gd.x_lo, gd.x_hi)
+    t = to_dev(psi0, s)
+    dt, n = 0.01, 80
+    obs = s.step(t, n, dt, obs_every=40)
+    V = oracle.ctap_potential(g.shape, g.lo, g.hi, gd.v0, gd.sigma, gd.xc)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, dt, n)
+    tol = 1e-12 if dtype == "c128" else 3 * 6e-8 * np.sqrt(5 * n)
+    assert rel(host(t), ref) < tol
+    o = oracle.observables(ref, V, g.lo, g.hi, gd.x_lo, gd.x_hi)
+    for a, key in enumerate(("p1", "p2", "p3")):
+        assert abs(obs[-1]["pop"][a] - o[key]) < (1e-12 if dtype == "c128" else 1e-6)
+    ekin = oracle.observables(ref, None, g.lo, g.hi, 0, 0)["energy"]
+    assert abs(obs[-1]["epot"] - (o["energy"] - ekin)) < (1e-9 if dtype == "c128" else 1e-4)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_gradient_vs_oracle(dtype):
+    say("adjoint", dtype)
+    g, gd, psi0 = _ctap_small()
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    dt, n, seg = 0.01, 40, 16
+    F_ref, G_ref, psiN_ref = oracle.adjoint_ctap(psi0, g.lo, g.hi, gd.v0, gd.sigma, gd.xc, dt, n, gd.x_hi)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_guides(gd.v0, gd.sigma, gd.xc)
+    s.set_partition(gd.x_lo, gd.x_hi)
+    psi = to_dev(psi0, s)
+    nseg = -(-n // seg)
+    ck = s.empty(nseg)
+    s.step_ckpt(psi, n, dt, seg, ck)
+    F = s.observables(psi)["pop"][2]
+    lam = s.empty()
+    s.adjoint_init(psi, lam)
+    G = torch.zeros(3 * g.n[2], dtype=torch.float64, device=DEV)
+    seq = s.empty(seg + 1)
+    for k in reversed(range(nseg)):
+        steps = min(seg, n - k * seg)
+        s.step_seq(ck[k], steps, dt, seq)
+        s.adjoint_segment(lam, seq, steps, dt, G)
+    Gh = G.cpu().numpy().reshape(3, g.n[2])
+    scale = np.max(np.abs(G_ref))
+    if dtype == "c128":
+        assert abs(F - F_ref) < 1e-12
+        assert np.max(np.abs(Gh - G_ref)) < 1e-10 * scale
+    else:
+        assert abs(F - F_ref) < 1e-6
+        assert np.max(np.abs(Gh - G_ref)) < 1e-4 * scale
+    s.close()
+
+
+def test_checkpoint_recompute_is_bitwise():
+    say("ckpt bitwise")
+    g, gd, psi0 = _ctap_small()
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    s.set_guides(gd.v0, gd.sigma, gd.xc)
+    dt, n, every = 0.01, 24, 8
+    psi = to_dev(psi0, s)
+    ck = s.empty(3)
+    s.step_ckpt(psi, n, dt, every, ck)
+    seq = s.empty(every + 1)
+    s.step_seq(ck[1], every, dt, seq)
+    assert torch.equal(seq[every], ck[2])
+    s.step_seq(ck[2], every, dt, seq)
+    assert torch.equal(seq[every], psi)
+    s.close()
