@@ -177,6 +177,11 @@ ssf_status ssf_adjoint_init(ssf_handle* h, const void* psi, void* lambda);
 ssf_status ssf_adjoint_segment(ssf_handle* h, void* lambda, const void* seq_dev, int64_t nsteps,
                                double dt, double* G_dev);
 
+/* Chain rule to profile coefficients: out_dev[g][m] = sum_z G_dev[g][z] B_dev[z][m]
+ * for g < nguides, m < M (device FP64 buffers; B_dev is (Nz, M) row-major). */
+ssf_status ssf_profile_grad(ssf_handle* h, const double* G_dev, int32_t nguides, const double* B_dev, int32_t M,
+                            double* out_dev);
+
 /* Host helper: clamped uniform cubic B-spline basis on [a, b] with M >= 4
  * functions evaluated at z[0..nz-1]; B_out is (nz, M) row-major, FP64. */
 ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int32_t nz, double* B_out);

@@ -213,5 +213,16 @@ class Solver:
         _ssf.call("ssf_adjoint_segment", self.h, self._field(lam, "lambda"), ctypes.c_void_p(seq.data_ptr()),
                   int(nsteps), float(dt), ctypes.c_void_p(G.data_ptr()))
 
+    def profile_grad(self, G, B, nguides, out):
+        """out[g, m] = sum_z G[g, z] B[z, m] on the device (FP64 tensors)."""
+        torch = self.torch
+        for t in (G, B, out):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("profile_grad needs contiguous float64 tensors on the solver's device")
+        M = B.shape[1]
+        self._sync_stream()
+        _ssf.call("ssf_profile_grad", self.h, ctypes.c_void_p(G.data_ptr()), int(nguides),
+                  ctypes.c_void_p(B.data_ptr()), int(M), ctypes.c_void_p(out.data_ptr()))
+
     def sync(self):
         _ssf.call("ssf_sync", self.h)

@@ -32,7 +32,7 @@ EXPORTS = (
     "ssf_set_potential_table", "ssf_set_potential_ctap", "ssf_clear_potential",
     "ssf_set_partition", "ssf_set_fusion", "ssf_set_timing", "ssf_timing_read", "ssf_step", "ssf_fft", "ssf_observables",
     "ssf_obs_read", "ssf_sync", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
-    "ssf_adjoint_segment", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
+    "ssf_adjoint_segment", "ssf_profile_grad", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
 )
 
 
@@ -103,6 +103,7 @@ def load():
         "ssf_step_seq": ([hp, vp, i64, dbl, vp], i32),
         "ssf_adjoint_init": ([hp, vp, vp], i32),
         "ssf_adjoint_segment": ([hp, vp, vp, i64, dbl, vp], i32),
+        "ssf_profile_grad": ([hp, vp, i32, vp, i32, vp], i32),
         "ssf_bspline_basis": ([i32, dbl, dbl, dp, i32, dp], i32),
         "ssf_status_string": ([i32], ctypes.c_char_p),
         "ssf_last_error": ([], ctypes.c_char_p),

@@ -45,9 +45,9 @@ struct PassArgs {
   const double2* kt[3];    // kinetic factors per axis (FFT bin order); 1/N folded into kt[2]
   int vkind;
   const void* vtab;        // (nz, ny, nx) potential table (f64 or f32)
-  const double* ctapA;     // (g, nz, nx): v0_g exp(-(x - xc_g(z))^2 / (2 s_g^2))
-  const double* ctapD;     // (g, nz, nx): ctapA * (x - xc_g(z)) / s_g^2
-  const double* ctapB;     // (g, ny):     exp(-y^2 / (2 s_g^2))
+  const double* ctapA;     // (MAX_GUIDES, nz, nx): v0_g exp(-(x - xc_g(z))^2 / (2 s_g^2)), 0 if unused
+  const double* ctapD;     // (MAX_GUIDES, nz, nx): ctapA * (x - xc_g(z)) / s_g^2
+  const double* ctapB;     // (MAX_GUIDES, ny): exp(-y^2 / (2 s_g^2))
   int nguides;
   const double* scale;     // device scalar multiplier (PRE_SCALE)
   double* partials;        // per-workgroup FP64 partial sums

@@ -22,6 +22,8 @@
 // px * sizeof(storage) contiguous bytes.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
+
 #include "ssf_internal.hpp"
 
 namespace ssf {
@@ -277,13 +279,14 @@ __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   pc = fma(pc, r2, -1.0 / 24.0);                  // 1/4!
   pc = fma(pc, r2, 0.5);                          // 1/2!
   const double cr = fma(-pc, r2, 1.0);
+  // quadrant k = q mod 4: odd k swaps sin and cos; sin changes sign for
+  // k = 2, 3 and cos for k = 1, 2
   const int k = (int)((long long)q & 3);
-  double ss = sr, cc = cr;
-  if (k == 1) { ss = cr; cc = -sr; }
-  else if (k == 2) { ss = -sr; cc = -cr; }
-  else if (k == 3) { ss = -cr; cc = sr; }
-  *s = ss;
-  *c = cc;
+  const bool swap = (k & 1) != 0;
+  const double sgn_s = (k & 2) ? -1.0 : 1.0;
+  const double sgn_c = ((k + 1) & 2) ? -1.0 : 1.0;
+  *s = sgn_s * (swap ? cr : sr);
+  *c = sgn_c * (swap ? sr : cr);
 }
 __device__ __forceinline__ double2 phase_factor(double theta, int imag) {
   if (imag) return make_double2(exp(-theta), 0.0);
@@ -292,17 +295,84 @@ __device__ __forceinline__ double2 phase_factor(double theta, int imag) {
   return make_double2(c, -s);
 }
 
+// Potential at grid point (x, y, z).  The guide tables always hold MAX_GUIDES
+// guides; unused guides have zero depth.
 __device__ __forceinline__ double potential_at(const PassArgs& a, int x, int y, int z) {
   switch (a.vkind) {
     case V_TAB64: return ((const double*)a.vtab)[((long long)z * a.ny + y) * a.nx + x];
     case V_TAB32: return (double)((const float*)a.vtab)[((long long)z * a.ny + y) * a.nx + x];
     case V_CTAP: {
-      double v = 0.0;
-      for (int j = 0; j < a.nguides; ++j)
-        v -= a.ctapA[((long long)j * a.nz + z) * a.nx + x] * a.ctapB[(long long)j * a.ny + y];
-      return v;
+      const long long pl = (long long)a.nz * a.nx, o = (long long)z * a.nx + x;
+      return -(a.ctapA[o] * a.ctapB[y] + a.ctapA[pl + o] * a.ctapB[a.ny + y] +
+               a.ctapA[2 * pl + o] * a.ctapB[2 * a.ny + y]);
     }
     default: return 0.0;
+  }
+}
+
+// Potentials of the E values a thread holds in the layout of a radix-r stage
+// of an x pass: value (u, m) sits at x = iu[u] + m N/r of row yu[u] in plane z.
+// The source switch is taken once, outside the element loops.
+template <int N, int E, int r>
+__device__ __forceinline__ void row_potentials(const PassArgs& a, const int (&iu)[E], const int (&yu)[E], int z,
+                                               double (&V)[E]) {
+  if (a.vkind == V_CTAP) {
+    const long long pl = (long long)a.nz * a.nx;
+    const double* __restrict__ A = a.ctapA + (long long)z * a.nx;
+#pragma unroll
+    for (int u = 0; u < E / r; ++u) {
+      const int y = yu[u];
+      const double b0 = a.ctapB[y], b1 = a.ctapB[a.ny + y], b2 = a.ctapB[2 * a.ny + y];
+#pragma unroll
+      for (int m = 0; m < r; ++m) {
+        const int x = iu[u] + m * (N / r);
+        V[u * r + m] = -(A[x] * b0 + A[pl + x] * b1 + A[2 * pl + x] * b2);
+      }
+    }
+  } else if (a.vkind == V_TAB64) {
+    const double* __restrict__ T = (const double*)a.vtab;
+#pragma unroll
+    for (int u = 0; u < E / r; ++u)
+#pragma unroll
+      for (int m = 0; m < r; ++m)
+        V[u * r + m] = T[((long long)z * a.ny + yu[u]) * a.nx + iu[u] + m * (N / r)];
+  } else if (a.vkind == V_TAB32) {
+    const float* __restrict__ T = (const float*)a.vtab;
+#pragma unroll
+    for (int u = 0; u < E / r; ++u)
+#pragma unroll
+      for (int m = 0; m < r; ++m)
+        V[u * r + m] = (double)T[((long long)z * a.ny + yu[u]) * a.nx + iu[u] + m * (N / r)];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) V[e] = 0.0;
+  }
+}
+
+// acc[g] -= dV/dxc_g-weight: sum over the thread's values of
+// D_g(x, z) B_g(y) Im(conj(lambda) psi)  (dV/dxc_g = -D_g B_g).
+template <int N, int E, int r, typename S>
+__device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 (&lam)[E], const int (&iu)[E],
+                                               const int (&yu)[E], const bool (&ok)[E], const long long (&base)[E],
+                                               int z, double* acc) {
+  const S* __restrict__ aux = (const S*)a.aux;
+  const long long pl = (long long)a.nz * a.nx;
+  const double* __restrict__ D = a.ctapD + (long long)z * a.nx;
+#pragma unroll
+  for (int u = 0; u < E / r; ++u) {
+    if (!ok[u]) continue;
+    const int y = yu[u];
+    const double b0 = a.ctapB[y], b1 = a.ctapB[a.ny + y], b2 = a.ctapB[2 * a.ny + y];
+#pragma unroll
+    for (int m = 0; m < r; ++m) {
+      const int x = iu[u] + m * (N / r);
+      const double2 l = lam[u * r + m];
+      const double2 w = ld2(aux + base[u] + x);
+      const double im = l.x * w.y - l.y * w.x;  // Im(conj(lambda) psi)
+      acc[0] -= D[x] * b0 * im;
+      acc[1] -= D[pl + x] * b1 * im;
+      acc[2] -= D[2 * pl + x] * b2 * im;
+    }
   }
 }
 
@@ -364,14 +434,24 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[Plan<N>::E], const do
     G::template map<r>(threadIdx.x + G::WG * u, b, i);
     double2* x = &v[u * r];
     if constexpr (p > 1) {
+      // input m is multiplied by w^m, w = exp(sign 2 pi i k / (p r)) = W[k N/(p r)].
+      // w^1, w^2, w^4, w^8 come from the table (exactly rounded); every other
+      // power is the product of its highest power-of-two part and the rest.
       const int k = i % p;
       constexpr int step = N / (p * r);
+      double2 w[r];
 #pragma unroll
-      for (int m = 1; m < r; ++m) {
-        double2 w = tw[m * k * step];
-        if constexpr (INV) w.y = -w.y;
-        x[m] = cmul(x[m], w);
+      for (int m = 1; m < r; m <<= 1) {
+        w[m] = tw[m * k * step];
+        if constexpr (INV) w[m].y = -w[m].y;
       }
+#pragma unroll
+      for (int m = 3; m < r; ++m) {
+        const int hp = 1 << (31 - __builtin_clz(m));
+        if (hp != m) w[m] = cmul(w[hp], w[m - hp]);
+      }
+#pragma unroll
+      for (int m = 1; m < r; ++m) x[m] = cmul(x[m], w[m]);
     }
     Bfly<r, INV>::run(x);
   }
@@ -432,7 +512,9 @@ __device__ __forceinline__ void transform(double2 (&v)[Plan<N>::E], double2* lds
 
 // Pass kernel.  FUSED: transform (direction INV1) - mid op - transform
 // (opposite direction, reversed radix order).  Not FUSED: one transform in
-// direction INV1.
+// direction INV1.  Pointwise ops (potential phase, scale, reductions) exist
+// for x passes (CONTIG); strided passes carry the kinetic factor and the
+// kinetic-energy sum of z pencils.
 template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1>
 __global__ void __launch_bounds__(PX * PO * N / Plan<N>::E)
 pass_kernel(PassArgs a) {
@@ -440,29 +522,39 @@ pass_kernel(PassArgs a) {
   using PL = Plan<N>;
   constexpr int E = G::E, WG = G::WG, P = G::P;
   constexpr int r_first = PL::R[0];                                // first stage of the first transform
+  constexpr int rm = PL::R[PL::S - 1];                             // last stage of the first transform
   constexpr int r_last = FUSED ? PL::R[0] : PL::R[PL::S - 1];      // last stage of the last transform
-  constexpr int NRED = CONTIG ? NRED_OBS : 1;
 
   __shared__ double2 lds[G::LDS];
   __shared__ double red[((WG + 63) / 64) * NRED_OBS];
 
   const S* __restrict__ in = (const S*)a.in;
   S* __restrict__ out = (S*)a.out;
-
-  // Tile origin.
   const int t0 = blockIdx.x, t1 = blockIdx.y;
-  // pencil b -> (valid, base offset, pencil coordinates)
-  auto pencil = [&](int b, long long& base, int& c0, int& c1) -> bool {
-    if constexpr (CONTIG) {
-      const int y = t0 * P + b, z = t1;
-      c0 = y; c1 = z;
-      base = ((long long)z * a.ny + y) * a.nx;
-      return y < a.ny;
-    } else {
-      const int x = t0 * PX + (b % PX), o = t1 * PO + (b / PX);
-      c0 = x; c1 = o;
-      base = (long long)o * a.ostride + x;
-      return x < a.nx && o < a.nouter;
+
+  // Per-butterfly pencil data in the layout of a radix-r stage:
+  //   contiguous: row y = t0 P + b of plane z = t1 (clamped for ragged tiles);
+  //   strided:    column x = t0 PX + b % PX of outer pencil o = t1 PO + b / PX.
+  auto pencils = [&](auto rtag, int (&iu)[E], int (&c0)[E], int (&c1)[E], bool (&ok)[E], long long (&base)[E]) {
+    constexpr int r = decltype(rtag)::value;
+#pragma unroll
+    for (int u = 0; u < E / r; ++u) {
+      int b, i;
+      G::template map<r>(threadIdx.x + WG * u, b, i);
+      iu[u] = i;
+      if constexpr (CONTIG) {
+        const int y = t0 * P + b;
+        ok[u] = y < a.ny;
+        c0[u] = ok[u] ? y : a.ny - 1;
+        c1[u] = t1;
+        base[u] = ((long long)t1 * a.ny + c0[u]) * a.nx;
+      } else {
+        const int x = t0 * PX + (b % PX), o = t1 * PO + (b / PX);
+        ok[u] = x < a.nx && o < a.nouter;
+        c0[u] = x < a.nx ? x : a.nx - 1;
+        c1[u] = o < a.nouter ? o : a.nouter - 1;
+        base[u] = (long long)c1[u] * a.ostride + c0[u];
+      }
     }
   };
   auto elem = [&](long long base, int n) -> long long {
@@ -473,62 +565,61 @@ pass_kernel(PassArgs a) {
   double acc[NRED_OBS];
 #pragma unroll
   for (int q = 0; q < NRED_OBS; ++q) acc[q] = 0.0;
-
   double2 v[E];
-  // ---- load (stage-0 inputs of the first transform) + pre ops ----
+
+  // ---- load the stage-0 inputs of the first transform, then pre ops ----
+  {
+    constexpr int r = r_first;
+    int iu[E], c0[E], c1[E];
+    bool ok[E];
+    long long base[E];
+    pencils(std::integral_constant<int, r>{}, iu, c0, c1, ok, base);
 #pragma unroll
-  for (int u = 0; u < E / r_first; ++u) {
-    int b, i;
-    G::template map<r_first>(threadIdx.x + WG * u, b, i);
-    long long base; int c0, c1;
-    const bool ok = pencil(b, base, c0, c1);
+    for (int u = 0; u < E / r; ++u)
 #pragma unroll
-    for (int m = 0; m < r_first; ++m) {
-      const int n = i + m * (N / r_first);
-      double2 val = make_double2(0.0, 0.0);
-      if (ok) {
-        const long long e = elem(base, n);
-        val = ld2(in + e);
-        if constexpr (CONTIG) {
-          if (a.pre & PRE_ADJ) {
-            const double2 w = ld2((const S*)a.aux + e);
-            const double im = val.x * w.y - val.y * w.x;   // Im(conj(lambda) psi)
-            for (int j = 0; j < a.nguides; ++j)
-              acc[j] -= a.ctapD[((long long)j * a.nz + c1) * a.nx + n] * a.ctapB[(long long)j * a.ny + c0] * im;
-          }
-          if (a.pre & PRE_SCALE) val = cscale(val, *a.scale);
-          if (a.pre & PRE_VPHASE) val = cmul(val, phase_factor(potential_at(a, n, c0, c1) * a.cpre, a.imag));
-        }
+      for (int m = 0; m < r; ++m)
+        v[u * r + m] = ok[u] ? ld2(in + elem(base[u], iu[u] + m * (N / r))) : make_double2(0.0, 0.0);
+    if constexpr (CONTIG) {
+      if (a.pre & PRE_ADJ) {
+        adj_accumulate<N, E, r, S>(a, v, iu, c0, ok, base, t1, acc);
       }
-      v[u * r_first + m] = val;
+      if (a.pre & PRE_SCALE) {
+        const double sc = *a.scale;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
+      }
+      if (a.pre & PRE_VPHASE) {
+        double V[E];
+        row_potentials<N, E, r>(a, iu, c0, t1, V);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpre, a.imag));
+      }
     }
   }
 
   transform<S, N, PX, PO, CONTIG, INV1, false>(v, lds, a.tw);
 
   if constexpr (FUSED) {
-    // outputs of the last stage sit at n = i + q N / r, r = PL::R[S-1]
-    constexpr int rm = PL::R[PL::S - 1];
+    // outputs of the last stage sit at n = i + q N / rm
+    constexpr int r = rm;
+    int iu[E], c0[E], c1[E];
+    bool ok[E];
+    long long base[E];
+    pencils(std::integral_constant<int, r>{}, iu, c0, c1, ok, base);
+    if constexpr (CONTIG) {
+      if (a.mid == MID_VPHASE) {
+        double V[E];
+        row_potentials<N, E, r>(a, iu, c0, t1, V);
 #pragma unroll
-    for (int u = 0; u < E / rm; ++u) {
-      int b, i;
-      G::template map<rm>(threadIdx.x + WG * u, b, i);
-      long long base; int c0, c1;
-      pencil(b, base, c0, c1);
+        for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cmid, a.imag));
+      }
+    } else {
+      if (a.mid == MID_KINETIC) {
 #pragma unroll
-      for (int q = 0; q < rm; ++q) {
-        const int n = i + q * (N / rm);
-        double2& val = v[u * rm + q];
-        if constexpr (CONTIG) {
-          if (a.mid == MID_VPHASE) {
-            const int y = c0 < a.ny ? c0 : a.ny - 1;
-            val = cmul(val, phase_factor(potential_at(a, n, y, c1) * a.cmid, a.imag));
-          }
-        } else {
-          if (a.mid == MID_KINETIC) {
-            const int x = c0 < a.nx ? c0 : a.nx - 1, y = c1 < a.nouter ? c1 : a.nouter - 1;
-            val = cmul(val, cmul(cmul(a.kt[0][x], a.kt[1][y]), a.kt[2][n]));
-          }
+        for (int u = 0; u < E / r; ++u) {
+          const double2 kxy = cmul(a.kt[0][c0[u]], a.kt[1][c1[u]]);
+#pragma unroll
+          for (int q = 0; q < r; ++q) v[u * r + q] = cmul(v[u * r + q], cmul(kxy, a.kt[2][iu[u] + q * (N / r)]));
         }
       }
     }
@@ -536,60 +627,81 @@ pass_kernel(PassArgs a) {
   }
 
   // ---- post ops + store (outputs of the last stage at n = i + q N / r_last) ----
+  {
+    constexpr int r = r_last;
+    int iu[E], c0[E], c1[E];
+    bool ok[E];
+    long long base[E];
+    pencils(std::integral_constant<int, r>{}, iu, c0, c1, ok, base);
+    if constexpr (CONTIG) {
+      double V[E];
+      if (a.post & (POST_VPHASE | POST_OBS)) {
+        row_potentials<N, E, r>(a, iu, c0, t1, V);
+      }
+      if (a.post & POST_VPHASE) {
 #pragma unroll
-  for (int u = 0; u < E / r_last; ++u) {
-    int b, i;
-    G::template map<r_last>(threadIdx.x + WG * u, b, i);
-    long long base; int c0, c1;
-    const bool ok = pencil(b, base, c0, c1);
+        for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpost, a.imag));
+      }
+      if (a.post & POST_OBS) {
+        const double zc = a.lo[2] + t1 * a.d[2];
 #pragma unroll
-    for (int q = 0; q < r_last; ++q) {
-      const int n = i + q * (N / r_last);
-      double2 val = v[u * r_last + q];
-      if (ok) {
-        const long long e = elem(base, n);
-        if constexpr (CONTIG) {
-          double V = 0.0;
-          if (a.post & (POST_VPHASE | POST_OBS)) V = potential_at(a, n, c0, c1);
-          if (a.post & POST_VPHASE) val = cmul(val, phase_factor(V * a.cpost, a.imag));
-          const double2 sv = rounded(val, out);
-          if (a.post & POST_OBS) {
-            const double rho = sv.x * sv.x + sv.y * sv.y;
+        for (int u = 0; u < E / r; ++u) {
+          const double w = ok[u] ? 1.0 : 0.0;
+          const double yc = a.lo[1] + c0[u] * a.d[1];
+#pragma unroll
+          for (int q = 0; q < r; ++q) {
+            const int n = iu[u] + q * (N / r);
+            const double2 sv = rounded(v[u * r + q], out);
+            const double rho = w * (sv.x * sv.x + sv.y * sv.y);
             acc[0] += rho;
             acc[1] += (a.lo[0] + n * a.d[0]) * rho;
-            acc[2] += (a.lo[1] + c0 * a.d[1]) * rho;
-            acc[3] += (a.lo[2] + c1 * a.d[2]) * rho;
-            if (n < a.ix_lo) acc[4] += rho;
-            else if (n > a.ix_hi) acc[6] += rho;
-            else acc[5] += rho;
-            acc[7] += V * rho;
-          }
-          if (a.post & POST_ADJ) {
-            const double2 w = ld2((const S*)a.aux + e);
-            const double im = sv.x * w.y - sv.y * w.x;
-            for (int j = 0; j < a.nguides; ++j)
-              acc[j] -= a.ctapD[((long long)j * a.nz + c1) * a.nx + n] * a.ctapB[(long long)j * a.ny + c0] * im;
-          }
-        } else {
-          if (a.post & POST_KIN) {
-            // z pencils of a field transformed along x and y: bins (c0, c1, n)
-            const int mx = 2 * c0 < a.nx ? c0 : c0 - a.nx;
-            const int my = 2 * c1 < a.ny ? c1 : c1 - a.ny;
-            const int mz = 2 * n < a.nz ? n : n - a.nz;
-            const double kx = a.kfac[0] * mx, ky = a.kfac[1] * my, kz = a.kfac[2] * mz;
-            acc[0] += 0.5 * (kx * kx + ky * ky + kz * kz) * (val.x * val.x + val.y * val.y);
+            acc[2] += yc * rho;
+            acc[3] += zc * rho;
+            acc[4] += n < a.ix_lo ? rho : 0.0;
+            acc[6] += n > a.ix_hi ? rho : 0.0;
+            acc[5] += (n >= a.ix_lo && n <= a.ix_hi) ? rho : 0.0;
+            acc[7] += V[u * r + q] * rho;
           }
         }
-        st2(out + e, val);
       }
+      if (a.post & POST_ADJ) {
+        double2 sv[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) sv[e] = rounded(v[e], out);
+        adj_accumulate<N, E, r, S>(a, sv, iu, c0, ok, base, t1, acc);
+      }
+    } else {
+      if (a.post & POST_KIN) {
+        // z pencils of a field transformed along x and y: bins (c0, c1, n)
+#pragma unroll
+        for (int u = 0; u < E / r; ++u) {
+          const double w = ok[u] ? 0.5 : 0.0;
+          const int mx = 2 * c0[u] < a.nx ? c0[u] : c0[u] - a.nx;
+          const int my = 2 * c1[u] < a.ny ? c1[u] : c1[u] - a.ny;
+          const double kx = a.kfac[0] * mx, ky = a.kfac[1] * my;
+#pragma unroll
+          for (int q = 0; q < r; ++q) {
+            const int n = iu[u] + q * (N / r);
+            const int mz = 2 * n < a.nz ? n : n - a.nz;
+            const double kz = a.kfac[2] * mz;
+            const double2 val = v[u * r + q];
+            acc[0] += w * (kx * kx + ky * ky + kz * kz) * (val.x * val.x + val.y * val.y);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < E / r; ++u) {
+      if (!ok[u]) continue;
+#pragma unroll
+      for (int q = 0; q < r; ++q) st2(out + elem(base[u], iu[u] + q * (N / r)), v[u * r + q]);
     }
   }
 
-  if (a.post & (POST_OBS | POST_ADJ | POST_KIN) || (a.pre & PRE_ADJ)) {
+  if ((a.post & (POST_OBS | POST_ADJ | POST_KIN)) || (a.pre & PRE_ADJ)) {
     double* dst = a.partials + (long long)(blockIdx.y * gridDim.x + blockIdx.x) * NRED_OBS;
     block_sum<WG, NRED_OBS>(acc, dst, red);
   }
-  (void)NRED;
 }
 
 // ---------------------------------------------------------------------------

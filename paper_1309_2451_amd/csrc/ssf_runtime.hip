@@ -152,6 +152,17 @@ __global__ void adj_finalize(const double* partials, int ytiles, int nz, int ngu
   G[(long long)g * nz + z] += w * s;
 }
 
+// out[g][m] = sum_z G[g][z] B[z][m]: chain rule from guide centres to the
+// coefficients of x_g(z) = sum_m c_gm B_m(z).  One thread per (g, m), z in order.
+__global__ void profile_grad_kernel(const double* G, const double* B, int nz, int M, int ng, double* out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ng * M) return;
+  const int g = t / M, m = t % M;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += G[(long long)g * nz + z] * B[(long long)z * M + m];
+  out[t] = s;
+}
+
 // Norm, moments, populations and potential energy of a stored field, with the
 // same partial layout as the x pass: block (y tile of `rows` rows, plane z).
 template <typename S>
@@ -278,7 +289,7 @@ PassArgs base_args(const ssf_handle* h, const void* in, void* out, int axis) {
   a.vkind = h->vkind;
   a.vtab = h->vtab;
   if (h->ctap) {
-    const long long plane = (long long)h->nguides * h->n[2] * h->n[0];
+    const long long plane = (long long)ssf::MAX_GUIDES * h->n[2] * h->n[0];
     a.ctapA = h->ctap;
     a.ctapD = h->ctap + plane;
     a.ctapB = h->ctap + 2 * plane;
@@ -569,9 +580,10 @@ ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d) {
   if (d->nguides < 1 || d->nguides > ssf::MAX_GUIDES) return fail(SSF_E_INVALID, "nguides must be 1..3");
   for (int g = 0; g < d->nguides; ++g)
     if (!(d->sigma[g] > 0.0) || !std::isfinite(d->v0[g])) return fail(SSF_E_INVALID, "sigma must be > 0, v0 finite");
+  // The kernels always evaluate MAX_GUIDES guides: unused ones get zero tables.
   const int nx = h->n[0], ny = h->n[1], nz = h->n[2], ng = d->nguides;
-  const long long plane = (long long)ng * nz * nx;
-  std::vector<double> tab(2 * plane + (long long)ng * ny);
+  const long long plane = (long long)ssf::MAX_GUIDES * nz * nx;
+  std::vector<double> tab(2 * plane + (long long)ssf::MAX_GUIDES * ny, 0.0);
   for (int g = 0; g < ng; ++g) {
     const double s2 = d->sigma[g] * d->sigma[g];
     for (int z = 0; z < nz; ++z) {
@@ -802,6 +814,18 @@ ssf_status ssf_adjoint_segment(ssf_handle* h, void* lambda, const void* seq_dev,
                        (int)gx.x, h->n[2], h->nguides, w, G_dev);
     HIP_TRY(hipGetLastError());
   }
+  return SSF_OK;
+}
+
+ssf_status ssf_profile_grad(ssf_handle* h, const double* G_dev, int32_t nguides, const double* B_dev, int32_t M,
+                            double* out_dev) {
+  SSF_TRY(check_handle(h));
+  if (!G_dev || !B_dev || !out_dev || M < 1 || nguides < 1 || nguides > ssf::MAX_GUIDES)
+    return fail(SSF_E_INVALID, "bad profile gradient arguments");
+  const int n = nguides * M;
+  hipLaunchKernelGGL(profile_grad_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, h->stream, G_dev, B_dev, h->n[2],
+                     M, nguides, out_dev);
+  HIP_TRY(hipGetLastError());
   return SSF_OK;
 }
 

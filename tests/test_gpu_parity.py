@@ -273,3 +273,38 @@ def test_checkpoint_recompute_is_bitwise():
     s.step_seq(ck[2], every, dt, seq)
     assert torch.equal(seq[every], psi)
     s.close()
+
+
+def test_fidelity_autograd_fd_and_oracle_chain_rule():
+    say("fidelity autograd c128")
+    from paper_1309_2451_amd.fidelity import FidelityFn, FidelityProblem
+    g, gd, psi0 = _ctap_small()
+    M = 8
+    a, b = g.lo[2], g.hi[2]
+    zg = synth.greville(M, a, b)
+    prof = synth.ctap_profile(zg, 2.0, 0.6, 2.0, -2.0, 3.0)
+    coeffs = np.stack([prof[0], prof[2]])
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128")
+    dt, n, every = 0.01, 30, 8
+    prob = FidelityProblem(s, to_dev(psi0, s), gd.v0, gd.sigma, np.zeros(g.n[2]), M, (a, b), gd.x_lo, gd.x_hi,
+                           dt, n, every)
+    c = torch.tensor(coeffs, dtype=torch.float64, requires_grad=True)
+    F = FidelityFn.apply(c, prob)
+    F.backward()
+    grad = c.grad.numpy()
+    # oracle: F and dF/dxc on the same profile, chain rule with the oracle's own B-splines
+    xc = prob.profile(coeffs)
+    F_ref, G_ref, _ = oracle.adjoint_ctap(psi0, g.lo, g.hi, gd.v0, gd.sigma, xc, dt, n, gd.x_hi)
+    Bo = oracle.bspline_basis(M, a, b, g.axis(2))
+    grad_ref = np.stack([G_ref[0] @ Bo, G_ref[2] @ Bo])
+    assert abs(float(F) - F_ref) < 1e-12
+    assert np.max(np.abs(grad - grad_ref)) < 1e-10 * np.max(np.abs(grad_ref))
+    # central finite differences through the GPU forward path
+    for k, m in [(0, 3), (1, 4)]:
+        h = 1e-4
+        cp, cm = coeffs.copy(), coeffs.copy()
+        cp[k, m] += h
+        cm[k, m] -= h
+        fd = (prob.forward(cp) - prob.forward(cm)) / (2 * h)
+        assert abs(fd - grad[k, m]) < 1e-6 * max(1.0, abs(fd)), (k, m, fd, grad[k, m])
+    s.close()
