@@ -66,6 +66,8 @@ def run_mode(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device):
     s = ssf.Solver(g.n, g.lo, g.hi, dtype, device=device)
     s.set_guides(gd.v0, gd.sigma, gd.xc)
     s.set_partition(gd.x_lo, gd.x_hi)
+    tiles, tune_us = s.tune(reps=10)          # tile autotuner (outside the timed region)
+    s.tune_result = {"choice": tiles, "us": {"axis%d_variant%d" % k: v for k, v in tune_us.items()}}
     psi = psi0.to(s.tdtype).contiguous().clone()
     obs = s.obs_buffer(max(1, (steps + warmup) // obs_every))
     if warmup:
@@ -119,6 +121,10 @@ def main():
     ap.add_argument("--grid", type=str, default="256,256,512", help="Nx,Ny,Nz of the guide workload")
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison run")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--imag-steps", type=int, default=None,
+                    help="imaginary-time steps of the transverse ground state (default: the workload's 2000)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of one field (for scaling profiler byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % a.gpus,
@@ -134,6 +140,8 @@ def main():
     device = "cuda:0"
     n = tuple(int(v) for v in a.grid.split(","))
     cfg = synth.config2(n)
+    if a.imag_steps is not None:
+        cfg["imag_steps"] = a.imag_steps
     g = cfg["grid"]
     print("bench: building initial state on %s" % (g.n,), file=sys.stderr, flush=True)
     psi0 = initial_state(torch, ssf, cfg, torch.complex128, device)
@@ -175,6 +183,7 @@ def main():
         "step_algorithmic_gbs": step_gbs,
         "passes_per_step": launches / a.steps,
         "pass_times_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in pass64.items()},
+        "tiles": s64.tune_result,
     }
     if rec64 is not None and len(rec64):
         out["final_populations"] = [float(v) for v in rec64[-1]["pop"]]
@@ -196,6 +205,14 @@ def main():
         out["c64_vs_c128_rel_l2"] = relL2
         out["c64_vs_c128_steps"] = a.steps + a.warmup
         s128.close()
+    if a.calibrate_copy:
+        # a plain copy of one complex64 field: 2 * 8 * points bytes of HBM traffic per launch
+        src = psi64.contiguous()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * src.numel() * src.element_size()
     s64.close()
 
     if a.cpu_steps > 0:

@@ -123,6 +123,19 @@ ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi);
  * rounding. */
 ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
 
+/* Tile autotuner.  The y and z passes come in NUM variants of tile shape
+ * (0: 128 B of storage per row segment; 1: half-width tile, twice the values
+ * per thread, twice as many workgroups fit a compute unit).  ssf_tune times
+ * every variant of the y pass (forward) and of the z pass (forward-kinetic-
+ * inverse) `reps` times on a field-sized workspace (allocated on first use),
+ * keeps the fastest per axis, writes the choice to choice_out[3] (x is
+ * always 0) and, if us_out != NULL, the average microseconds per launch to
+ * us_out[axis * 2 + variant] (6 entries).  Synchronises the stream.
+ * ssf_set_tiles / ssf_get_tiles set and read the choice (e.g. from a cache). */
+ssf_status ssf_tune(ssf_handle* h, int32_t reps, int32_t* choice_out, double* us_out);
+ssf_status ssf_set_tiles(ssf_handle* h, const int32_t* choice);
+ssf_status ssf_get_tiles(ssf_handle* h, int32_t* choice);
+
 /* Pass timing for measurement: while on, every pass launch is bracketed by
  * a pair of HIP events on the handle's stream.  ssf_timing_read synchronises
  * the stream and returns, per pass kind, the summed kernel time in ms and the

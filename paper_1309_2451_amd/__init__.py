@@ -140,6 +140,24 @@ class Solver:
     def set_fusion(self, on: bool):
         _ssf.call("ssf_set_fusion", self.h, 1 if on else 0)
 
+    def tune(self, reps=5):
+        """Time every y/z tile variant on this grid and keep the fastest.
+        Returns (choice[3], {(axis, variant): microseconds})."""
+        self._sync_stream()
+        ch = np.zeros(3, dtype=np.int32)
+        us = np.zeros(6, dtype=np.float64)
+        _ssf.call("ssf_tune", self.h, int(reps), ctypes.c_void_p(ch.ctypes.data), ctypes.c_void_p(us.ctypes.data))
+        return ch.tolist(), {(a, v): float(us[a * 2 + v]) for a in (1, 2) for v in (0, 1)}
+
+    def set_tiles(self, choice):
+        ch = np.ascontiguousarray(choice, dtype=np.int32)
+        _ssf.call("ssf_set_tiles", self.h, ctypes.c_void_p(ch.ctypes.data))
+
+    def get_tiles(self):
+        ch = np.zeros(3, dtype=np.int32)
+        _ssf.call("ssf_get_tiles", self.h, ctypes.c_void_p(ch.ctypes.data))
+        return ch.tolist()
+
     PASS_KINDS = ("x_fwd", "x_inv", "x_inv_phase_fwd", "yz_fwd", "yz_inv", "z_fwd_kin_inv")
 
     def set_timing(self, on: bool):

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libssf.so")
+# SSF_LIBRARY may point at another build of the same library (e.g. a tile variant)
+LIB_PATH = os.environ.get("SSF_LIBRARY") or os.path.join(_HERE, "libssf.so")
 
 SSF_OK = 0
 SSF_E_INVALID = -1
@@ -30,7 +31,8 @@ SSF_IMAG = 1
 EXPORTS = (
     "ssf_supported_length", "ssf_create", "ssf_destroy", "ssf_set_stream",
     "ssf_set_potential_table", "ssf_set_potential_ctap", "ssf_clear_potential",
-    "ssf_set_partition", "ssf_set_fusion", "ssf_set_timing", "ssf_timing_read", "ssf_step", "ssf_fft", "ssf_observables",
+    "ssf_set_partition", "ssf_set_fusion", "ssf_set_timing", "ssf_timing_read",
+    "ssf_tune", "ssf_set_tiles", "ssf_get_tiles", "ssf_step", "ssf_fft", "ssf_observables",
     "ssf_obs_read", "ssf_sync", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
 )
@@ -93,6 +95,9 @@ def load():
         "ssf_set_partition": ([hp, dbl, dbl], i32),
         "ssf_set_fusion": ([hp, i32], i32),
         "ssf_set_timing": ([hp, i32], i32),
+        "ssf_tune": ([hp, i32, vp, vp], i32),
+        "ssf_set_tiles": ([hp, vp], i32),
+        "ssf_get_tiles": ([hp, vp], i32),
         "ssf_timing_read": ([hp, vp, vp], i32),
         "ssf_step": ([hp, vp, i64, dbl, i32, i64, vp], i32),
         "ssf_fft": ([hp, vp, i32, i32], i32),

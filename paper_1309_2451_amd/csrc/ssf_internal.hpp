@@ -54,6 +54,7 @@ struct PassArgs {
   double lo[3], d[3];      // grid origin and spacing
   double kfac[3];          // 2 pi / L per axis
   int ix_lo, ix_hi;        // P1: ix < ix_lo, P3: ix > ix_hi, P2 otherwise
+  int tiles_x, tiles_y;    // tile grid (set by the launcher); partial sums are per tile
 };
 
 // Tile geometry and launcher for one transform length and one storage type.
@@ -62,11 +63,16 @@ struct PassShape {
   int threads;             // workgroup size
 };
 
+// Strided tile variants (chosen per axis by the autotuner): 0 = px columns of
+// 128 B of storage; 1 = half as many columns, twice the values per thread.
+constexpr int NUM_STRIDED_VARIANTS = 2;
+
 struct KernelSet {
   int N;
-  PassShape contig[2];     // [dtype]: 0 = complex64 storage, 1 = complex128
-  PassShape strided[2];
-  hipError_t (*launch)(int kind, int dt_index, const PassArgs& a, dim3 grid, hipStream_t s);
+  PassShape contig[2];                             // [dtype]: 0 = complex64 storage, 1 = complex128
+  PassShape strided[2][NUM_STRIDED_VARIANTS];      // [dtype][variant]
+  // `tiles` = (tiles_x, tiles_y); the launcher picks the persistent grid.
+  hipError_t (*launch)(int kind, int dt_index, int variant, const PassArgs& a, dim3 tiles, hipStream_t s);
 };
 
 // Every supported transform length.  The kernel TU is compiled once per entry.

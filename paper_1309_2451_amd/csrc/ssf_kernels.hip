@@ -12,7 +12,7 @@
 // Instantiating the launcher in both compilation passes emits every pass
 // kernel of this length into the device code object.
 namespace ssf {
-template hipError_t launch_any<SSF_N>(int, int, const PassArgs&, dim3, hipStream_t);
+template hipError_t launch_any<SSF_N>(int, int, int, const PassArgs&, dim3, hipStream_t);
 }  // namespace ssf
 
 // The launcher table is host data.

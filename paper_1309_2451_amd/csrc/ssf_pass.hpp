@@ -78,18 +78,28 @@ template <class PL, bool REV> struct Order {
 constexpr int LDS_CAP_ELEMS = 8192;       // 128 KiB of double2
 template <int N> struct Shape {
   static constexpr int E = Plan<N>::E;
-  static constexpr int sx(int dt) {        // strided tile width in x
-    int px = dt == 0 ? 16 : 8;             // 128 B of storage per row segment
+  static constexpr int sx0(int dt) {               // variant-0 tile width in x
+    int px = dt == 0 ? 16 : 8;                      // 128 B of storage per row segment
     while (px > 1 && px * N > LDS_CAP_ELEMS) px /= 2;
     return px;
   }
-  static constexpr int so(int dt) {        // strided tile depth (outer pencils)
-    int po = 256 * E / (N * sx(dt));
+  static constexpr int so(int dt, int var = 0) {   // strided tile depth (outer pencils)
+    int po = 256 * E / (N * sx0(dt));
     if (po < 1) po = 1;
-    while (po > 1 && sx(dt) * po * N > LDS_CAP_ELEMS) po /= 2;
-    while (po > 1 && sx(dt) * po * N / E > 1024) po /= 2;
+    while (po > 1 && sx0(dt) * po * N > LDS_CAP_ELEMS) po /= 2;
+    while (po > 1 && sx0(dt) * po * N / E > 1024) po /= 2;
     return po;
   }
+  static constexpr int sm0(int dt) {               // variant-0 values-per-thread multiplier
+    int em = 1;
+    while (sx0(dt) * so(dt) * N / (E * em) > 512) em *= 2;
+    return em;
+  }
+  // variant 1 (half-width tile, twice the values per thread) exists when the
+  // doubled value count still divides N
+  static constexpr bool v1(int dt) { return sx0(dt) > 1 && N % (E * sm0(dt) * 2) == 0; }
+  static constexpr int sx(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sx0(dt) / 2 : sx0(dt); }
+  static constexpr int sm(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sm0(dt) * 2 : sm0(dt); }
   static constexpr int ldrow() { return N + N / 8 + (N >= 8 ? 0 : 0); }
   static constexpr int cr() {              // contiguous rows per workgroup
     int rows = 256 * E / N;
@@ -255,29 +265,26 @@ template <bool INV> struct Bfly<5, INV> {
 constexpr double TWO_OVER_PI = 0.63661977236758134308;
 constexpr double PIO2_HI = 1.5707963267948966192;       // nearest double to pi/2
 constexpr double PIO2_LO = 6.123233995736766036e-17;    // pi/2 - PIO2_HI
+// Taylor coefficients (-1)^k / (2k+1)! for sin (k = 8..1) and (-1)^k / (2k)!
+// for cos (k = 9..1), read from constant memory so that they stay in scalar
+// registers instead of vector registers.
+__constant__ double SINCOS_C[17] = {
+    1.0 / 355687428096000.0, -1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0,
+    1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,
+    1.0 / 6402373705728000.0, -1.0 / 20922789888000.0, 1.0 / 87178291200.0, -1.0 / 479001600.0,
+    1.0 / 3628800.0, -1.0 / 40320.0, 1.0 / 720.0, -1.0 / 24.0, 0.5};
 __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   const double q = rint(t * TWO_OVER_PI);
   double r = fma(-q, PIO2_HI, t);
   r = fma(-q, PIO2_LO, r);
   const double r2 = r * r;
-  double ps = 1.0 / 355687428096000.0;            // 1/17!
-  ps = fma(ps, r2, -1.0 / 1307674368000.0);       // 1/15!
-  ps = fma(ps, r2, 1.0 / 6227020800.0);           // 1/13!
-  ps = fma(ps, r2, -1.0 / 39916800.0);            // 1/11!
-  ps = fma(ps, r2, 1.0 / 362880.0);               // 1/9!
-  ps = fma(ps, r2, -1.0 / 5040.0);                // 1/7!
-  ps = fma(ps, r2, 1.0 / 120.0);                  // 1/5!
-  ps = fma(ps, r2, -1.0 / 6.0);                   // 1/3!
+  double ps = SINCOS_C[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
   const double sr = fma(ps * r2, r, r);
-  double pc = 1.0 / 6402373705728000.0;           // 1/18!
-  pc = fma(pc, r2, -1.0 / 20922789888000.0);      // 1/16!
-  pc = fma(pc, r2, 1.0 / 87178291200.0);          // 1/14!
-  pc = fma(pc, r2, -1.0 / 479001600.0);           // 1/12!
-  pc = fma(pc, r2, 1.0 / 3628800.0);              // 1/10!
-  pc = fma(pc, r2, -1.0 / 40320.0);               // 1/8!
-  pc = fma(pc, r2, 1.0 / 720.0);                  // 1/6!
-  pc = fma(pc, r2, -1.0 / 24.0);                  // 1/4!
-  pc = fma(pc, r2, 0.5);                          // 1/2!
+  double pc = SINCOS_C[8];
+#pragma unroll
+  for (int k = 9; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
   const double cr = fma(-pc, r2, 1.0);
   // quadrant k = q mod 4: odd k swaps sin and cos; sin changes sign for
   // k = 2, 3 and cos for k = 1, 2
@@ -288,11 +295,16 @@ __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   *s = sgn_s * (swap ? cr : sr);
   *c = sgn_c * (swap ? sr : cr);
 }
-__device__ __forceinline__ double2 phase_factor(double theta, int imag) {
-  if (imag) return make_double2(exp(-theta), 0.0);
+// exp(-i theta)
+__device__ __forceinline__ double2 phase_rt(double theta) {
   double s, c;
   sincos_fast(theta, &s, &c);
   return make_double2(c, -s);
+}
+// exp(-i theta) in real time, exp(-theta) in imaginary time
+__device__ __forceinline__ double2 phase_factor(double theta, int imag) {
+  if (imag) return make_double2(exp(-theta), 0.0);
+  return phase_rt(theta);
 }
 
 // Potential at grid point (x, y, z).  The guide tables always hold MAX_GUIDES
@@ -307,72 +319,6 @@ __device__ __forceinline__ double potential_at(const PassArgs& a, int x, int y, 
                a.ctapA[2 * pl + o] * a.ctapB[2 * a.ny + y]);
     }
     default: return 0.0;
-  }
-}
-
-// Potentials of the E values a thread holds in the layout of a radix-r stage
-// of an x pass: value (u, m) sits at x = iu[u] + m N/r of row yu[u] in plane z.
-// The source switch is taken once, outside the element loops.
-template <int N, int E, int r>
-__device__ __forceinline__ void row_potentials(const PassArgs& a, const int (&iu)[E], const int (&yu)[E], int z,
-                                               double (&V)[E]) {
-  if (a.vkind == V_CTAP) {
-    const long long pl = (long long)a.nz * a.nx;
-    const double* __restrict__ A = a.ctapA + (long long)z * a.nx;
-#pragma unroll
-    for (int u = 0; u < E / r; ++u) {
-      const int y = yu[u];
-      const double b0 = a.ctapB[y], b1 = a.ctapB[a.ny + y], b2 = a.ctapB[2 * a.ny + y];
-#pragma unroll
-      for (int m = 0; m < r; ++m) {
-        const int x = iu[u] + m * (N / r);
-        V[u * r + m] = -(A[x] * b0 + A[pl + x] * b1 + A[2 * pl + x] * b2);
-      }
-    }
-  } else if (a.vkind == V_TAB64) {
-    const double* __restrict__ T = (const double*)a.vtab;
-#pragma unroll
-    for (int u = 0; u < E / r; ++u)
-#pragma unroll
-      for (int m = 0; m < r; ++m)
-        V[u * r + m] = T[((long long)z * a.ny + yu[u]) * a.nx + iu[u] + m * (N / r)];
-  } else if (a.vkind == V_TAB32) {
-    const float* __restrict__ T = (const float*)a.vtab;
-#pragma unroll
-    for (int u = 0; u < E / r; ++u)
-#pragma unroll
-      for (int m = 0; m < r; ++m)
-        V[u * r + m] = (double)T[((long long)z * a.ny + yu[u]) * a.nx + iu[u] + m * (N / r)];
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) V[e] = 0.0;
-  }
-}
-
-// acc[g] -= dV/dxc_g-weight: sum over the thread's values of
-// D_g(x, z) B_g(y) Im(conj(lambda) psi)  (dV/dxc_g = -D_g B_g).
-template <int N, int E, int r, typename S>
-__device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 (&lam)[E], const int (&iu)[E],
-                                               const int (&yu)[E], const bool (&ok)[E], const long long (&base)[E],
-                                               int z, double* acc) {
-  const S* __restrict__ aux = (const S*)a.aux;
-  const long long pl = (long long)a.nz * a.nx;
-  const double* __restrict__ D = a.ctapD + (long long)z * a.nx;
-#pragma unroll
-  for (int u = 0; u < E / r; ++u) {
-    if (!ok[u]) continue;
-    const int y = yu[u];
-    const double b0 = a.ctapB[y], b1 = a.ctapB[a.ny + y], b2 = a.ctapB[2 * a.ny + y];
-#pragma unroll
-    for (int m = 0; m < r; ++m) {
-      const int x = iu[u] + m * (N / r);
-      const double2 l = lam[u * r + m];
-      const double2 w = ld2(aux + base[u] + x);
-      const double im = l.x * w.y - l.y * w.x;  // Im(conj(lambda) psi)
-      acc[0] -= D[x] * b0 * im;
-      acc[1] -= D[pl + x] * b1 * im;
-      acc[2] -= D[2 * pl + x] * b2 * im;
-    }
   }
 }
 
@@ -398,16 +344,20 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double* dst, double
     for (int w = 0; w < NW; ++w) s += red[w * NV + threadIdx.x];
     dst[threadIdx.x] = s;
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // The pass kernel.
 // ---------------------------------------------------------------------------
-template <typename S, int N, int PX, int PO, bool CONTIG>
+template <typename S, int N, int PX, int PO, bool CONTIG, int EM = 1>
 struct PassGeom {
   using PL = Plan<N>;
+  static constexpr int NN = N;
+  static constexpr bool CONTIGUOUS = CONTIG;
+  static constexpr int PXX = PX, POO = PO;
   static constexpr int P = PX * PO;
-  static constexpr int E = PL::E;
+  static constexpr int E = PL::E * EM;
   static constexpr int WG = P * N / E;
   static constexpr int LDROW = Shape<N>::ldrow();
   static constexpr int LDS = PL::S > 1 ? (CONTIG ? P * LDROW : P * N) : 1;
@@ -423,9 +373,9 @@ struct PassGeom {
   }
 };
 
-template <typename S, int N, int PX, int PO, bool CONTIG, bool INV, class ORD, int s>
-__device__ __forceinline__ void compute_stage(double2 (&v)[Plan<N>::E], const double2* __restrict__ tw) {
-  using G = PassGeom<S, N, PX, PO, CONTIG>;
+template <class G, bool INV, class ORD, int s>
+__device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2* __restrict__ tw) {
+  constexpr int N = G::NN;
   constexpr int r = ORD::r(s), p = ORD::p(s);
   constexpr int E = G::E;
 #pragma unroll
@@ -458,9 +408,9 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[Plan<N>::E], const do
 }
 
 // Write the outputs of stage s-1 to LDS and read the inputs of stage s.
-template <typename S, int N, int PX, int PO, bool CONTIG, class ORD, int s>
-__device__ __forceinline__ void exchange(double2 (&v)[Plan<N>::E], double2* lds) {
-  using G = PassGeom<S, N, PX, PO, CONTIG>;
+template <class G, class ORD, int s>
+__device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds) {
+  constexpr int N = G::NN;
   constexpr int r1 = ORD::r(s - 1), p1 = ORD::p(s - 1);
   constexpr int r2 = ORD::r(s);
   constexpr int E = G::E;
@@ -486,27 +436,133 @@ __device__ __forceinline__ void exchange(double2 (&v)[Plan<N>::E], double2* lds)
 
 // All stages of one transform direction; v holds the inputs of stage 0 on
 // entry and the outputs of the last stage on exit.
-template <typename S, int N, int PX, int PO, bool CONTIG, bool INV, bool REV>
-__device__ __forceinline__ void transform(double2 (&v)[Plan<N>::E], double2* lds, const double2* __restrict__ tw) {
-  using ORD = Order<Plan<N>, REV>;
-  constexpr int NS = Plan<N>::S;
+template <class G, bool INV, bool REV>
+__device__ __forceinline__ void transform(double2 (&v)[G::E], double2* lds, const double2* __restrict__ tw) {
+  using ORD = Order<Plan<G::NN>, REV>;
+  constexpr int NS = Plan<G::NN>::S;
   static_assert(NS <= 5, "at most 5 stages");
-  compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 0>(v, tw);
+  compute_stage<G, INV, ORD, 0>(v, tw);
   if constexpr (NS > 1) {
-    exchange<S, N, PX, PO, CONTIG, ORD, 1>(v, lds);
-    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 1>(v, tw);
+    exchange<G, ORD, 1>(v, lds);
+    compute_stage<G, INV, ORD, 1>(v, tw);
   }
   if constexpr (NS > 2) {
-    exchange<S, N, PX, PO, CONTIG, ORD, 2>(v, lds);
-    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 2>(v, tw);
+    exchange<G, ORD, 2>(v, lds);
+    compute_stage<G, INV, ORD, 2>(v, tw);
   }
   if constexpr (NS > 3) {
-    exchange<S, N, PX, PO, CONTIG, ORD, 3>(v, lds);
-    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 3>(v, tw);
+    exchange<G, ORD, 3>(v, lds);
+    compute_stage<G, INV, ORD, 3>(v, tw);
   }
   if constexpr (NS > 4) {
-    exchange<S, N, PX, PO, CONTIG, ORD, 4>(v, lds);
-    compute_stage<S, N, PX, PO, CONTIG, INV, ORD, 4>(v, tw);
+    exchange<G, ORD, 4>(v, lds);
+    compute_stage<G, INV, ORD, 4>(v, tw);
+  }
+}
+
+// The pencils a thread's values belong to in the layout of a radix-r stage:
+// value (u, m) is element n = i[u] + m N/r of pencil u, whose first element
+// sits at offset off[u] (32-bit: fields have fewer than 2^31 points).
+//   x passes:    row y = c0 of plane z = c1;
+//   y, z passes: column x = c0 of outer pencil c1 (z for y passes, y for z passes).
+// Ragged tiles clamp c0/c1 into range and clear ok.
+template <class G, int r> struct Pen {
+  static constexpr int U = G::E / r;
+  int i[U], c0[U], c1[U];
+  bool ok[U];
+  unsigned off[U];
+};
+
+template <class G, int r>
+__device__ __forceinline__ void pencils(Pen<G, r>& p, const PassArgs& a, int t) {
+  const int t0 = t % a.tiles_x, t1 = t / a.tiles_x;
+#pragma unroll
+  for (int u = 0; u < Pen<G, r>::U; ++u) {
+    int b, i;
+    G::template map<r>(threadIdx.x + G::WG * u, b, i);
+    p.i[u] = i;
+    if constexpr (G::CONTIGUOUS) {
+      const int y = t0 * G::P + b;
+      p.ok[u] = y < a.ny;
+      p.c0[u] = p.ok[u] ? y : a.ny - 1;
+      p.c1[u] = t1;
+      p.off[u] = ((unsigned)t1 * (unsigned)a.ny + (unsigned)p.c0[u]) * (unsigned)a.nx;
+    } else {
+      const int x = t0 * G::PXX + (b % G::PXX), o = t1 * G::POO + (b / G::PXX);
+      p.ok[u] = x < a.nx && o < a.nouter;
+      p.c0[u] = x < a.nx ? x : a.nx - 1;
+      p.c1[u] = o < a.nouter ? o : a.nouter - 1;
+      p.off[u] = (unsigned)p.c1[u] * (unsigned)a.ostride + (unsigned)p.c0[u];
+    }
+  }
+}
+
+template <class G>
+__device__ __forceinline__ unsigned elem_off(unsigned off, int n, const PassArgs& a) {
+  if constexpr (G::CONTIGUOUS) return off + (unsigned)n;
+  else return off + (unsigned)n * (unsigned)a.nstride;
+}
+
+// Potentials at a thread's values of an x pass (plane z).  Guide potential:
+// sA = A_g(x, z) for g < MAX_GUIDES, x < N and sB = B_g(y), both in LDS.
+// Tables: read from global memory.
+template <class G, int r>
+__device__ __forceinline__ void potentials(const PassArgs& a, const double* sA, const double* sB,
+                                           const Pen<G, r>& p, int z, double (&V)[G::E]) {
+  constexpr int N = G::NN, U = Pen<G, r>::U;
+  if (a.vkind == V_CTAP) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int y = p.c0[u];
+      const double b0 = sB[y], b1 = sB[a.ny + y], b2 = sB[2 * a.ny + y];
+#pragma unroll
+      for (int m = 0; m < r; ++m) {
+        const int x = p.i[u] + m * (N / r);
+        V[u * r + m] = -(sA[x] * b0 + sA[N + x] * b1 + sA[2 * N + x] * b2);
+      }
+    }
+  } else if (a.vkind == V_TAB64) {
+    const double* __restrict__ T = (const double*)a.vtab;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < r; ++m) V[u * r + m] = T[p.off[u] + p.i[u] + m * (N / r)];
+  } else if (a.vkind == V_TAB32) {
+    const float* __restrict__ T = (const float*)a.vtab;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < r; ++m) V[u * r + m] = (double)T[p.off[u] + p.i[u] + m * (N / r)];
+  } else {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) V[e] = 0.0;
+  }
+}
+
+// acc[g] += sum over the thread's values of dV/dxc_g Im(conj(lambda) psi),
+// dV/dxc_g = -D_g(x, z) B_g(y); psi is read from a.aux at the same offset.
+template <class G, int r, typename S>
+__device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 (&lam)[G::E], const Pen<G, r>& p,
+                                               int z, double* acc) {
+  constexpr int N = G::NN, U = Pen<G, r>::U;
+  const S* __restrict__ aux = (const S*)a.aux;
+  const long long pl = (long long)a.nz * a.nx;
+  const double* __restrict__ D = a.ctapD + (long long)z * a.nx;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (!p.ok[u]) continue;
+    const int y = p.c0[u];
+    const double b0 = a.ctapB[y], b1 = a.ctapB[a.ny + y], b2 = a.ctapB[2 * a.ny + y];
+#pragma unroll
+    for (int m = 0; m < r; ++m) {
+      const int x = p.i[u] + m * (N / r);
+      const double2 l = lam[u * r + m];
+      const double2 w = ld2(aux + p.off[u] + x);
+      const double im = l.x * w.y - l.y * w.x;  // Im(conj(lambda) psi)
+      acc[0] -= D[x] * b0 * im;
+      acc[1] -= D[pl + x] * b1 * im;
+      acc[2] -= D[2 * pl + x] * b2 * im;
+    }
   }
 }
 
@@ -515,247 +571,355 @@ __device__ __forceinline__ void transform(double2 (&v)[Plan<N>::E], double2* lds
 // direction INV1.  Pointwise ops (potential phase, scale, reductions) exist
 // for x passes (CONTIG); strided passes carry the kinetic factor and the
 // kinetic-energy sum of z pencils.
-template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1>
-__global__ void __launch_bounds__(PX * PO * N / Plan<N>::E)
+//
+// LEAN: only the mid op (potential phase from the guide tables in LDS, or
+// the kinetic factor); no pre/post ops, no reductions, no global tables.
+//
+// Persistent: workgroup w owns the contiguous tile range
+// [w C, (w+1) C), C = ceil(tiles / gridDim.x), tile t = (t % tiles_x,
+// t / tiles_x).  Twiddles, the z kinetic table and (x passes) the guide
+// tables live in LDS, so while a tile is transformed the only vector-memory
+// reads in flight are the prefetch of the next tile's values (and of its
+// per-pencil kinetic factors), which therefore overlap the arithmetic.
+template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN>
+__global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM))
 pass_kernel(PassArgs a) {
-  using G = PassGeom<S, N, PX, PO, CONTIG>;
+  using G = PassGeom<S, N, PX, PO, CONTIG, EM>;
   using PL = Plan<N>;
-  constexpr int E = G::E, WG = G::WG, P = G::P;
-  constexpr int r_first = PL::R[0];                                // first stage of the first transform
+  constexpr int E = G::E, WG = G::WG;
+  constexpr int r0 = PL::R[0];                                     // first stage of the first transform
   constexpr int rm = PL::R[PL::S - 1];                             // last stage of the first transform
-  constexpr int r_last = FUSED ? PL::R[0] : PL::R[PL::S - 1];      // last stage of the last transform
+  constexpr int rl = FUSED ? PL::R[0] : PL::R[PL::S - 1];          // last stage of the last transform
+  constexpr bool KZ = !CONTIG && FUSED;                            // z pass with the kinetic factor
+  constexpr int UM = E / rm;
 
   __shared__ double2 lds[G::LDS];
+  __shared__ double2 s_tw[N];
+  __shared__ double2 s_kz[KZ ? N : 1];
+  __shared__ double s_A[CONTIG ? MAX_GUIDES * N : 1];
   __shared__ double red[((WG + 63) / 64) * NRED_OBS];
+  extern __shared__ double s_dyn[];                                // x passes: B_g(y), MAX_GUIDES * ny
+
+  const int ntiles = a.tiles_x * a.tiles_y;
+  const int chunk = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int tbeg = (int)blockIdx.x * chunk;
+  const int tend = min(ntiles, tbeg + chunk);
+  if (tbeg >= tend) return;                                        // whole workgroup
 
   const S* __restrict__ in = (const S*)a.in;
   S* __restrict__ out = (S*)a.out;
-  const int t0 = blockIdx.x, t1 = blockIdx.y;
+  const bool ctap = CONTIG && a.vkind == V_CTAP;
 
-  // Per-butterfly pencil data in the layout of a radix-r stage:
-  //   contiguous: row y = t0 P + b of plane z = t1 (clamped for ragged tiles);
-  //   strided:    column x = t0 PX + b % PX of outer pencil o = t1 PO + b / PX.
-  auto pencils = [&](auto rtag, int (&iu)[E], int (&c0)[E], int (&c1)[E], bool (&ok)[E], long long (&base)[E]) {
-    constexpr int r = decltype(rtag)::value;
+  // tables into LDS (once per workgroup)
+  for (int j = threadIdx.x; j < N; j += WG) {
+    s_tw[j] = a.tw[j];
+    if constexpr (KZ) s_kz[j] = a.kt[2][j];
+  }
+  if constexpr (CONTIG) {
+    if (ctap)
+      for (int j = threadIdx.x; j < MAX_GUIDES * a.ny; j += WG) s_dyn[j] = a.ctapB[j];
+  }
+  const double pre_scale = (CONTIG && (a.pre & PRE_SCALE)) ? *a.scale : 1.0;
+  __syncthreads();
+
+  // raw stage-0 inputs (storage type) and, for the z pass, the per-pencil
+  // kinetic factors of the mid layout
+  // In y/z passes a thread always owns pencil b = threadIdx.x % P (the
+  // workgroup size is a multiple of P), so the z pass needs one per-pencil
+  // kinetic factor kx(x) ky(y) per thread and tile.
+  S raw[E];
+  double2 kx_n, ky_n;
+  auto load_tile = [&](int t) {
+    Pen<G, r0> p;
+    pencils(p, a, t);
 #pragma unroll
-    for (int u = 0; u < E / r; ++u) {
-      int b, i;
-      G::template map<r>(threadIdx.x + WG * u, b, i);
-      iu[u] = i;
+    for (int u = 0; u < E / r0; ++u)
+#pragma unroll
+      for (int m = 0; m < r0; ++m) {
+        S v;
+        v.x = 0;
+        v.y = 0;
+        if (p.ok[u]) v = in[elem_off<G>(p.off[u], p.i[u] + m * (N / r0), a)];
+        raw[u * r0 + m] = v;
+      }
+    if constexpr (KZ) {
+      static_assert(G::WG % G::P == 0, "one pencil per thread");
+      kx_n = a.kt[0][p.c0[0]];
+      ky_n = a.kt[1][p.c1[0]];
+    }
+  };
+  // the adjoint and global potential tables read global memory inside the
+  // tile, so those passes load each tile when they reach it
+  const bool prefetch = LEAN || !(CONTIG && ((a.pre & PRE_ADJ) || (a.post & POST_ADJ) ||
+                                             (!ctap && a.vkind != V_NONE)));
+
+  int plane = -1;
+  if (prefetch) load_tile(tbeg);
+  for (int t = tbeg; t < tend; ++t) {
+    const int t1 = t / a.tiles_x;
+    if constexpr (CONTIG) {
+      if (ctap && t1 != plane) {
+        // guide tables A_g(x, z) of this plane into LDS
+        __syncthreads();
+        const long long pl = (long long)a.nz * a.nx;
+        for (int j = threadIdx.x; j < MAX_GUIDES * N; j += WG)
+          s_A[j] = a.ctapA[(j / N) * pl + (long long)t1 * a.nx + (j % N)];
+        __syncthreads();
+        plane = t1;
+      }
+    }
+    if (!prefetch) load_tile(t);
+    double2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = make_double2((double)raw[e].x, (double)raw[e].y);
+    double2 kxy = make_double2(1.0, 0.0);
+    if constexpr (KZ) kxy = cmul(kx_n, ky_n);
+    if (prefetch && t + 1 < tend) load_tile(t + 1);
+
+    double acc[NRED_OBS];
+#pragma unroll
+    for (int q = 0; q < NRED_OBS; ++q) acc[q] = 0.0;
+
+    // ---- pre ops on the stage-0 inputs of the first transform ----
+    if constexpr (CONTIG && !LEAN) {
+      if (a.pre & (PRE_ADJ | PRE_SCALE | PRE_VPHASE)) {
+        Pen<G, r0> p;
+        pencils(p, a, t);
+        if (a.pre & PRE_ADJ) adj_accumulate<G, r0, S>(a, v, p, t1, acc);
+        if (a.pre & PRE_SCALE) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = cscale(v[e], pre_scale);
+        }
+        if (a.pre & PRE_VPHASE) {
+          double V[E];
+          potentials<G, r0>(a, s_A, s_dyn, p, t1, V);
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpre, a.imag));
+        }
+      }
+    }
+
+    transform<G, INV1, false>(v, lds, s_tw);
+
+    if constexpr (FUSED) {
+      // outputs of the last stage sit at n = i + q N / rm
       if constexpr (CONTIG) {
-        const int y = t0 * P + b;
-        ok[u] = y < a.ny;
-        c0[u] = ok[u] ? y : a.ny - 1;
-        c1[u] = t1;
-        base[u] = ((long long)t1 * a.ny + c0[u]) * a.nx;
+        if (a.mid == MID_VPHASE) {
+          Pen<G, rm> p;
+          pencils(p, a, t);
+          double V[E];
+          if constexpr (LEAN) {
+            // guide potential from LDS (the host selects LEAN only for it or for V = 0)
+#pragma unroll
+            for (int u = 0; u < UM; ++u) {
+              const int y = p.c0[u];
+              const double b0 = s_dyn[y], b1 = s_dyn[a.ny + y], b2 = s_dyn[2 * a.ny + y];
+#pragma unroll
+              for (int m = 0; m < rm; ++m) {
+                const int x = p.i[u] + m * (N / rm);
+                V[u * rm + m] = ctap ? -(s_A[x] * b0 + s_A[N + x] * b1 + s_A[2 * N + x] * b2) : 0.0;
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt(V[e] * a.cmid));
+          } else {
+            potentials<G, rm>(a, s_A, s_dyn, p, t1, V);
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cmid, a.imag));
+          }
+        }
       } else {
-        const int x = t0 * PX + (b % PX), o = t1 * PO + (b / PX);
-        ok[u] = x < a.nx && o < a.nouter;
-        c0[u] = x < a.nx ? x : a.nx - 1;
-        c1[u] = o < a.nouter ? o : a.nouter - 1;
-        base[u] = (long long)c1[u] * a.ostride + c0[u];
-      }
-    }
-  };
-  auto elem = [&](long long base, int n) -> long long {
-    if constexpr (CONTIG) return base + n;
-    else return base + (long long)n * a.nstride;
-  };
-
-  double acc[NRED_OBS];
+        if (a.mid == MID_KINETIC) {
 #pragma unroll
-  for (int q = 0; q < NRED_OBS; ++q) acc[q] = 0.0;
-  double2 v[E];
-
-  // ---- load the stage-0 inputs of the first transform, then pre ops ----
-  {
-    constexpr int r = r_first;
-    int iu[E], c0[E], c1[E];
-    bool ok[E];
-    long long base[E];
-    pencils(std::integral_constant<int, r>{}, iu, c0, c1, ok, base);
+          for (int u = 0; u < UM; ++u) {
+            int b, i;
+            G::template map<rm>(threadIdx.x + WG * u, b, i);
 #pragma unroll
-    for (int u = 0; u < E / r; ++u)
-#pragma unroll
-      for (int m = 0; m < r; ++m)
-        v[u * r + m] = ok[u] ? ld2(in + elem(base[u], iu[u] + m * (N / r))) : make_double2(0.0, 0.0);
-    if constexpr (CONTIG) {
-      if (a.pre & PRE_ADJ) {
-        adj_accumulate<N, E, r, S>(a, v, iu, c0, ok, base, t1, acc);
-      }
-      if (a.pre & PRE_SCALE) {
-        const double sc = *a.scale;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
-      }
-      if (a.pre & PRE_VPHASE) {
-        double V[E];
-        row_potentials<N, E, r>(a, iu, c0, t1, V);
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpre, a.imag));
-      }
-    }
-  }
-
-  transform<S, N, PX, PO, CONTIG, INV1, false>(v, lds, a.tw);
-
-  if constexpr (FUSED) {
-    // outputs of the last stage sit at n = i + q N / rm
-    constexpr int r = rm;
-    int iu[E], c0[E], c1[E];
-    bool ok[E];
-    long long base[E];
-    pencils(std::integral_constant<int, r>{}, iu, c0, c1, ok, base);
-    if constexpr (CONTIG) {
-      if (a.mid == MID_VPHASE) {
-        double V[E];
-        row_potentials<N, E, r>(a, iu, c0, t1, V);
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cmid, a.imag));
-      }
-    } else {
-      if (a.mid == MID_KINETIC) {
-#pragma unroll
-        for (int u = 0; u < E / r; ++u) {
-          const double2 kxy = cmul(a.kt[0][c0[u]], a.kt[1][c1[u]]);
-#pragma unroll
-          for (int q = 0; q < r; ++q) v[u * r + q] = cmul(v[u * r + q], cmul(kxy, a.kt[2][iu[u] + q * (N / r)]));
-        }
-      }
-    }
-    transform<S, N, PX, PO, CONTIG, !INV1, true>(v, lds, a.tw);
-  }
-
-  // ---- post ops + store (outputs of the last stage at n = i + q N / r_last) ----
-  {
-    constexpr int r = r_last;
-    int iu[E], c0[E], c1[E];
-    bool ok[E];
-    long long base[E];
-    pencils(std::integral_constant<int, r>{}, iu, c0, c1, ok, base);
-    if constexpr (CONTIG) {
-      double V[E];
-      if (a.post & (POST_VPHASE | POST_OBS)) {
-        row_potentials<N, E, r>(a, iu, c0, t1, V);
-      }
-      if (a.post & POST_VPHASE) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpost, a.imag));
-      }
-      if (a.post & POST_OBS) {
-        const double zc = a.lo[2] + t1 * a.d[2];
-#pragma unroll
-        for (int u = 0; u < E / r; ++u) {
-          const double w = ok[u] ? 1.0 : 0.0;
-          const double yc = a.lo[1] + c0[u] * a.d[1];
-#pragma unroll
-          for (int q = 0; q < r; ++q) {
-            const int n = iu[u] + q * (N / r);
-            const double2 sv = rounded(v[u * r + q], out);
-            const double rho = w * (sv.x * sv.x + sv.y * sv.y);
-            acc[0] += rho;
-            acc[1] += (a.lo[0] + n * a.d[0]) * rho;
-            acc[2] += yc * rho;
-            acc[3] += zc * rho;
-            acc[4] += n < a.ix_lo ? rho : 0.0;
-            acc[6] += n > a.ix_hi ? rho : 0.0;
-            acc[5] += (n >= a.ix_lo && n <= a.ix_hi) ? rho : 0.0;
-            acc[7] += V[u * r + q] * rho;
+            for (int q = 0; q < rm; ++q) v[u * rm + q] = cmul(v[u * rm + q], cmul(kxy, s_kz[i + q * (N / rm)]));
           }
         }
       }
-      if (a.post & POST_ADJ) {
-        double2 sv[E];
+      transform<G, !INV1, true>(v, lds, s_tw);
+    }
+
+    // ---- post ops + store (outputs of the last stage at n = i + q N / rl) ----
+    {
+      constexpr int r = rl;
+      Pen<G, r> p;
+      pencils(p, a, t);
+      if constexpr (LEAN) {
+      } else if constexpr (CONTIG) {
+        double V[E];
+        if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, p, t1, V);
+        if (a.post & POST_VPHASE) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) sv[e] = rounded(v[e], out);
-        adj_accumulate<N, E, r, S>(a, sv, iu, c0, ok, base, t1, acc);
-      }
-    } else {
-      if (a.post & POST_KIN) {
-        // z pencils of a field transformed along x and y: bins (c0, c1, n)
+          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpost, a.imag));
+        }
+        if (a.post & POST_OBS) {
+          const double zc = a.lo[2] + t1 * a.d[2];
 #pragma unroll
-        for (int u = 0; u < E / r; ++u) {
-          const double w = ok[u] ? 0.5 : 0.0;
-          const int mx = 2 * c0[u] < a.nx ? c0[u] : c0[u] - a.nx;
-          const int my = 2 * c1[u] < a.ny ? c1[u] : c1[u] - a.ny;
-          const double kx = a.kfac[0] * mx, ky = a.kfac[1] * my;
+          for (int u = 0; u < E / r; ++u) {
+            const double w = p.ok[u] ? 1.0 : 0.0;
+            const double yc = a.lo[1] + p.c0[u] * a.d[1];
 #pragma unroll
-          for (int q = 0; q < r; ++q) {
-            const int n = iu[u] + q * (N / r);
-            const int mz = 2 * n < a.nz ? n : n - a.nz;
-            const double kz = a.kfac[2] * mz;
-            const double2 val = v[u * r + q];
-            acc[0] += w * (kx * kx + ky * ky + kz * kz) * (val.x * val.x + val.y * val.y);
+            for (int q = 0; q < r; ++q) {
+              const int n = p.i[u] + q * (N / r);
+              const double2 sv = rounded(v[u * r + q], out);
+              const double rho = w * (sv.x * sv.x + sv.y * sv.y);
+              acc[0] += rho;
+              acc[1] += (a.lo[0] + n * a.d[0]) * rho;
+              acc[2] += yc * rho;
+              acc[3] += zc * rho;
+              acc[4] += n < a.ix_lo ? rho : 0.0;
+              acc[6] += n > a.ix_hi ? rho : 0.0;
+              acc[5] += (n >= a.ix_lo && n <= a.ix_hi) ? rho : 0.0;
+              acc[7] += V[u * r + q] * rho;
+            }
+          }
+        }
+        if (a.post & POST_ADJ) {
+          double2 sv[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) sv[e] = rounded(v[e], out);
+          adj_accumulate<G, r, S>(a, sv, p, t1, acc);
+        }
+      } else {
+        if (a.post & POST_KIN) {
+          // z pencils of a field transformed along x and y: bins (c0, c1, n)
+#pragma unroll
+          for (int u = 0; u < E / r; ++u) {
+            const double w = p.ok[u] ? 0.5 : 0.0;
+            const int mx = 2 * p.c0[u] < a.nx ? p.c0[u] : p.c0[u] - a.nx;
+            const int my = 2 * p.c1[u] < a.ny ? p.c1[u] : p.c1[u] - a.ny;
+            const double kx = a.kfac[0] * mx, ky = a.kfac[1] * my;
+#pragma unroll
+            for (int q = 0; q < r; ++q) {
+              const int n = p.i[u] + q * (N / r);
+              const int mz = 2 * n < a.nz ? n : n - a.nz;
+              const double kz = a.kfac[2] * mz;
+              const double2 val = v[u * r + q];
+              acc[0] += w * (kx * kx + ky * ky + kz * kz) * (val.x * val.x + val.y * val.y);
+            }
           }
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < E / r; ++u) {
-      if (!ok[u]) continue;
+      for (int u = 0; u < E / r; ++u) {
+        if (!p.ok[u]) continue;
 #pragma unroll
-      for (int q = 0; q < r; ++q) st2(out + elem(base[u], iu[u] + q * (N / r)), v[u * r + q]);
+        for (int q = 0; q < r; ++q) st2(out + elem_off<G>(p.off[u], p.i[u] + q * (N / r), a), v[u * r + q]);
+      }
     }
-  }
 
-  if ((a.post & (POST_OBS | POST_ADJ | POST_KIN)) || (a.pre & PRE_ADJ)) {
-    double* dst = a.partials + (long long)(blockIdx.y * gridDim.x + blockIdx.x) * NRED_OBS;
-    block_sum<WG, NRED_OBS>(acc, dst, red);
+    if constexpr (!LEAN) {
+      if ((a.post & (POST_OBS | POST_ADJ | POST_KIN)) || (a.pre & PRE_ADJ))
+        block_sum<WG, NRED_OBS>(acc, a.partials + (long long)t * NRED_OBS, red);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Launcher for one (N, storage) pair.
+// Launchers.  `tiles` is the tile grid (tiles_x, tiles_y); the launch uses as
+// many persistent workgroups as fit on the device at once (at most one per
+// tile).
 // ---------------------------------------------------------------------------
-template <typename S, int N, int DT>
-hipError_t launch_pass(int kind, const PassArgs& a, dim3 grid, hipStream_t st) {
-  constexpr int CR = Shape<N>::cr();
-  constexpr int SX = Shape<N>::sx(DT), SO = Shape<N>::so(DT);
-  switch (kind) {
-    case CONTIG_FWD:
-      hipLaunchKernelGGL((pass_kernel<S, N, CR, 1, true, false, false>), grid,
-                         dim3(PassGeom<S, N, CR, 1, true>::WG), 0, st, a);
-      break;
-    case CONTIG_INV:
-      hipLaunchKernelGGL((pass_kernel<S, N, CR, 1, true, false, true>), grid,
-                         dim3(PassGeom<S, N, CR, 1, true>::WG), 0, st, a);
-      break;
-    case CONTIG_FUSED:
-      hipLaunchKernelGGL((pass_kernel<S, N, CR, 1, true, true, true>), grid,
-                         dim3(PassGeom<S, N, CR, 1, true>::WG), 0, st, a);
-      break;
-    case STRIDED_FWD:
-      hipLaunchKernelGGL((pass_kernel<S, N, SX, SO, false, false, false>), grid,
-                         dim3(PassGeom<S, N, SX, SO, false>::WG), 0, st, a);
-      break;
-    case STRIDED_INV:
-      hipLaunchKernelGGL((pass_kernel<S, N, SX, SO, false, false, true>), grid,
-                         dim3(PassGeom<S, N, SX, SO, false>::WG), 0, st, a);
-      break;
-    case STRIDED_FUSED:
-      hipLaunchKernelGGL((pass_kernel<S, N, SX, SO, false, true, false>), grid,
-                         dim3(PassGeom<S, N, SX, SO, false>::WG), 0, st, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+inline int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cus = v > 0 ? v : 1;
+    else
+      cus = 1;
   }
+  return cus;
+}
+
+template <typename K>
+hipError_t launch_persistent(K kernel, int wg, size_t dyn, PassArgs a, dim3 tiles, hipStream_t st, int& occ) {
+  if (occ <= 0) {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kernel, wg, dyn) != hipSuccess || o < 1) o = 1;
+    occ = o;
+  }
+  a.tiles_x = (int)tiles.x;
+  a.tiles_y = (int)tiles.y;
+  const long long ntiles = (long long)tiles.x * tiles.y;
+  long long grid = (long long)occ * device_cus();
+  if (grid > ntiles) grid = ntiles;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(wg), dyn, st, a);
   return hipGetLastError();
 }
 
+// The lean x kernel serves the fused x pass of the steady-state steps (only
+// the potential phase, guide potential or none); lean y/z kernels serve
+// every strided pass without a reduction.
+template <typename S, int N, int DT, int VAR>
+hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t st) {
+  constexpr int SX = Shape<N>::sx(DT, VAR), SO = Shape<N>::so(DT, VAR), SM = Shape<N>::sm(DT, VAR);
+  constexpr int WGS = PassGeom<S, N, SX, SO, false, SM>::WG;
+  static int occ[4] = {0, 0, 0, 0};
+  switch (kind) {
+    case STRIDED_FWD:
+      if (a.post == 0)
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true>, WGS, 0, a, tiles, st, occ[0]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false>, WGS, 0, a, tiles, st, occ[1]);
+    case STRIDED_INV:
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true>, WGS, 0, a, tiles, st, occ[2]);
+    case STRIDED_FUSED:
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true>, WGS, 0, a, tiles, st, occ[3]);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// The lean x kernel serves the fused x pass of the steady-state steps (only
+// the potential phase, guide potential or none, real time); lean y/z kernels
+// serve every strided pass without a reduction.
+template <typename S, int N, int DT>
+hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hipStream_t st) {
+  constexpr int CR = Shape<N>::cr();
+  constexpr int WGC = PassGeom<S, N, CR, 1, true, 1>::WG;
+  const size_t dync = sizeof(double) * MAX_GUIDES * (size_t)a.ny;
+  static int occ[4] = {0, 0, 0, 0};
+  const bool lean_x = a.pre == 0 && a.post == 0 && !a.imag && (a.vkind == V_CTAP || a.vkind == V_NONE);
+  switch (kind) {
+    case CONTIG_FWD:
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, false, 1, false>, WGC, dync, a, tiles, st, occ[0]);
+    case CONTIG_INV:
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, true, 1, false>, WGC, dync, a, tiles, st, occ[1]);
+    case CONTIG_FUSED:
+      if (lean_x)
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true>, WGC, dync, a, tiles, st, occ[2]);
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false>, WGC, dync, a, tiles, st, occ[3]);
+    default:
+      return variant == 1 ? launch_strided<S, N, DT, 1>(kind, a, tiles, st)
+                          : launch_strided<S, N, DT, 0>(kind, a, tiles, st);
+  }
+}
+
 template <int N>
-hipError_t launch_any(int kind, int dt_index, const PassArgs& a, dim3 grid, hipStream_t st) {
-  return dt_index == 0 ? launch_pass<float2, N, 0>(kind, a, grid, st)
-                       : launch_pass<double2, N, 1>(kind, a, grid, st);
+hipError_t launch_any(int kind, int dt_index, int variant, const PassArgs& a, dim3 grid, hipStream_t st) {
+  return dt_index == 0 ? launch_pass<float2, N, 0>(kind, variant, a, grid, st)
+                       : launch_pass<double2, N, 1>(kind, variant, a, grid, st);
+}
+
+template <int N, int DT, int VAR>
+constexpr PassShape strided_shape() {
+  using S = typename std::conditional<DT == 0, float2, double2>::type;
+  return PassShape{Shape<N>::sx(DT, VAR), Shape<N>::so(DT, VAR),
+                   PassGeom<S, N, Shape<N>::sx(DT, VAR), Shape<N>::so(DT, VAR), false, Shape<N>::sm(DT, VAR)>::WG};
 }
 
 template <int N>
 constexpr KernelSet make_kernel_set() {
   return KernelSet{
       N,
-      {PassShape{Shape<N>::cr(), 1, PassGeom<float2, N, Shape<N>::cr(), 1, true>::WG},
-       PassShape{Shape<N>::cr(), 1, PassGeom<double2, N, Shape<N>::cr(), 1, true>::WG}},
-      {PassShape{Shape<N>::sx(0), Shape<N>::so(0), PassGeom<float2, N, Shape<N>::sx(0), Shape<N>::so(0), false>::WG},
-       PassShape{Shape<N>::sx(1), Shape<N>::so(1), PassGeom<double2, N, Shape<N>::sx(1), Shape<N>::so(1), false>::WG}},
+      {PassShape{Shape<N>::cr(), 1, PassGeom<float2, N, Shape<N>::cr(), 1, true, 1>::WG},
+       PassShape{Shape<N>::cr(), 1, PassGeom<double2, N, Shape<N>::cr(), 1, true, 1>::WG}},
+      {{strided_shape<N, 0, 0>(), strided_shape<N, 0, 1>()}, {strided_shape<N, 1, 0>(), strided_shape<N, 1, 1>()}},
       &launch_any<N>};
 }
 

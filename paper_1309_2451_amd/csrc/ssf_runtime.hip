@@ -241,6 +241,7 @@ struct ssf_handle {
   int nguides = 0;
   int ix_lo = -1, ix_hi = 1 << 30;     // default: everything in P2
   int fuse = 1;
+  int var[3] = {0, 0, 0};              // strided tile variant per axis (autotuned)
   double* partials = nullptr;          // workspace: 2 regions of part_cap blocks x 8 doubles
   long long part_cap = 0;
   double* dscal = nullptr;             // device scalars: [0] scale
@@ -256,13 +257,13 @@ namespace {
 long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
 // Grid of one pass kind over the handle's field.
-dim3 pass_grid(const ssf_handle* h, int axis) {
+dim3 pass_grid(const ssf_handle* h, int axis, int variant = -1) {
   const KernelSet* ks = h->ks[axis];
   if (axis == 0) {
     const int rows = ks->contig[h->dti].px;
     return dim3((unsigned)ceil_div(h->n[1], rows), (unsigned)h->n[2], 1);
   }
-  const auto& sh = ks->strided[h->dti];
+  const auto& sh = ks->strided[h->dti][variant < 0 ? h->var[axis] : variant];
   const int nouter = axis == 1 ? h->n[2] : h->n[1];
   return dim3((unsigned)ceil_div(h->n[0], sh.px), (unsigned)ceil_div(nouter, sh.po), 1);
 }
@@ -323,7 +324,7 @@ ssf_status launch(ssf_handle* h, int kind, int axis, const PassArgs& a) {
     ++used;
     HIP_TRY(hipEventRecord(e0, h->stream));
   }
-  hipError_t e = h->ks[axis]->launch(kind, h->dti, a, g, h->stream);
+  hipError_t e = h->ks[axis]->launch(kind, h->dti, h->var[axis], a, g, h->stream);
   if (e != hipSuccess) return fail(SSF_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
   if (h->timing) HIP_TRY(hipEventRecord(e1, h->stream));
   return SSF_OK;
@@ -460,7 +461,8 @@ ssf_status ssf_create(const ssf_grid_desc* grid, int32_t dtype, void* hip_stream
     if (!find_kernels(grid->n[a]))
       return fail(SSF_E_UNSUPPORTED, "transform length " + std::to_string(grid->n[a]) + " is not supported");
   }
-  if ((long long)grid->n[1] > 0 && grid->n[2] > 65535) return fail(SSF_E_INVALID, "Nz must be <= 65535");
+  if ((long long)grid->n[0] * grid->n[1] * grid->n[2] >= (1LL << 31))
+    return fail(SSF_E_INVALID, "grids must have fewer than 2^31 points");
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(SSF_E_NODEVICE, "no HIP device visible");
   ssf_handle* h = new ssf_handle();
@@ -493,7 +495,11 @@ ssf_status ssf_create(const ssf_grid_desc* grid, int32_t dtype, void* hip_stream
       return cleanup(fail(SSF_E_DEVICE, "twiddle upload"));
   }
   long long cap = 0;
-  for (int a = 0; a < 3; ++a) cap = std::max(cap, blocks_of(h, a));
+  for (int a = 0; a < 3; ++a)
+    for (int v = 0; v < ssf::NUM_STRIDED_VARIANTS; ++v) {
+      const dim3 g = pass_grid(h, a, v);
+      cap = std::max(cap, (long long)g.x * g.y);
+    }
   h->part_cap = cap;
   if (hipMalloc(&h->partials, sizeof(double) * 8 * cap * 2) != hipSuccess)
     return cleanup(fail(SSF_E_NOMEM, "partials workspace"));
@@ -550,6 +556,76 @@ ssf_status ssf_timing_read(ssf_handle* h, double* ms_total, int64_t* launches) {
     launches[k] = (int64_t)h->ev_used[k];
     h->ev_used[k] = 0;
   }
+  return SSF_OK;
+}
+
+ssf_status ssf_set_tiles(ssf_handle* h, const int32_t* choice) {
+  SSF_TRY(check_handle(h));
+  if (!choice) return fail(SSF_E_INVALID, "null tile choice");
+  for (int a = 1; a < 3; ++a)
+    if (choice[a] < 0 || choice[a] >= ssf::NUM_STRIDED_VARIANTS) return fail(SSF_E_INVALID, "tile variant out of range");
+  h->var[1] = choice[1];
+  h->var[2] = choice[2];
+  return SSF_OK;
+}
+
+ssf_status ssf_get_tiles(ssf_handle* h, int32_t* choice) {
+  SSF_TRY(check_handle(h));
+  if (!choice) return fail(SSF_E_INVALID, "null tile choice");
+  for (int a = 0; a < 3; ++a) choice[a] = h->var[a];
+  return SSF_OK;
+}
+
+ssf_status ssf_tune(ssf_handle* h, int32_t reps, int32_t* choice_out, double* us_out) {
+  SSF_TRY(check_handle(h));
+  if (reps < 1) return fail(SSF_E_INVALID, "reps must be >= 1");
+  if (!h->work) HIP_TRY(hipMalloc(&h->work, h->esize * h->npts));
+  HIP_TRY(hipMemsetAsync(h->work, 0, h->esize * h->npts, h->stream));
+  const double2* kt = nullptr;
+  SSF_TRY(get_ktab(h, 1e-3, 0, &kt));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int saved_timing = h->timing;
+  h->timing = 0;
+  ssf_status st = SSF_OK;
+  for (int a = 1; a < 3 && st == SSF_OK; ++a) {
+    double best = 1e300;
+    int best_v = 0;
+    for (int v = 0; v < ssf::NUM_STRIDED_VARIANTS && st == SSF_OK; ++v) {
+      h->var[a] = v;
+      PassArgs pa = base_args(h, h->work, h->work, a);
+      int kind = ssf::STRIDED_FWD;
+      if (a == 2) {
+        kind = ssf::STRIDED_FUSED;
+        pa.mid = ssf::MID_KINETIC;
+        pa.kt[0] = kt;
+        pa.kt[1] = kt + h->n[0];
+        pa.kt[2] = kt + h->n[0] + h->n[1];
+      }
+      st = launch(h, kind, a, pa);                       // warm-up
+      if (st != SSF_OK) break;
+      if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(SSF_E_DEVICE, "event record"); break; }
+      for (int r = 0; r < reps && st == SSF_OK; ++r) st = launch(h, kind, a, pa);
+      if (st != SSF_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(SSF_E_DEVICE, "event timing");
+        break;
+      }
+      const double us = 1e3 * ms / reps;
+      if (us_out) us_out[a * ssf::NUM_STRIDED_VARIANTS + v] = us;
+      if (us < best) { best = us; best_v = v; }
+    }
+    h->var[a] = best_v;
+  }
+  h->timing = saved_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SSF_OK) { h->var[1] = h->var[2] = 0; return st; }
+  if (choice_out)
+    for (int a = 0; a < 3; ++a) choice_out[a] = h->var[a];
   return SSF_OK;
 }
 

@@ -308,3 +308,39 @@ def test_fidelity_autograd_fd_and_oracle_chain_rule():
         fd = (prob.forward(cp) - prob.forward(cm)) / (2 * h)
         assert abs(fd - grad[k, m]) < 1e-6 * max(1.0, abs(fd)), (k, m, fd, grad[k, m])
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", [(16, 32, 64), (12, 20, 40), (64, 24, 32), (20, 12, 96), (4, 12, 512)])
+def test_tile_variants_and_tuner(dtype, shape):
+    say("tile variants", dtype, shape)
+    nz, ny, nx = shape
+    g = synth.Grid((nx, ny, nz), (-4.0, -3.0, -5.0), (4.0, 3.0, 5.0))
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
+    psi0 = synth.random_field(g, 9, smooth=2.0)
+    V = rng.uniform(-8, 8, g.shape)
+    if dtype == "c64":
+        x, psi0 = c64_round(x), c64_round(psi0)
+    tol_fft = 1e-13 if dtype == "c128" else 2e-7
+    tol_step = 1e-12 if dtype == "c128" else 3 * 6e-8 * np.sqrt(5 * 20)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    ref_step, _ = oracle.step(psi0, V, g.lo, g.hi, 0.01, 20)
+    for choice in ([0, 1, 1], [0, 0, 1], [0, 1, 0]):
+        s.set_tiles(choice)
+        assert s.get_tiles() == choice
+        for axis in (1, 2):
+            t = to_dev(x, s)
+            s.fft(t, axes=(axis,))
+            assert rel(host(t), oracle.fft_axis(x, axis, -1)) < tol_fft, (choice, axis)
+        t = to_dev(psi0, s)
+        s.step(t, 20, 0.01)
+        assert rel(host(t), ref_step) < tol_step, choice
+    choice, us = s.tune(reps=2)
+    assert choice[0] == 0 and choice[1] in (0, 1) and choice[2] in (0, 1)
+    assert all(v > 0 for v in us.values())
+    t = to_dev(psi0, s)
+    s.step(t, 20, 0.01)
+    assert rel(host(t), ref_step) < tol_step
+    s.close()
