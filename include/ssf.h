@@ -124,8 +124,8 @@ ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi);
 ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
 
 /* Tile autotuner.  The y and z passes come in NUM variants of tile shape
- * (0: 128 B of storage per row segment; 1: half-width tile, twice the values
- * per thread, twice as many workgroups fit a compute unit).  ssf_tune times
+ * (0: 128 B of storage per row segment; 1: half-width tile, half the
+ * workgroup and LDS, so twice as many workgroups fit a compute unit).  ssf_tune times
  * every variant of the y pass (forward) and of the z pass (forward-kinetic-
  * inverse) `reps` times on a field-sized workspace (allocated on first use),
  * keeps the fastest per axis, writes the choice to choice_out[3] (x is
@@ -194,6 +194,31 @@ ssf_status ssf_adjoint_segment(ssf_handle* h, void* lambda, const void* seq_dev,
  * for g < nguides, m < M (device FP64 buffers; B_dev is (Nz, M) row-major). */
 ssf_status ssf_profile_grad(ssf_handle* h, const double* G_dev, int32_t nguides, const double* B_dev, int32_t M,
                             double* out_dev);
+
+/* Batched parameter sweeps (Sec. V, Fig. 6: final target population over a
+ * range of chip parameters; Sec. IV: concurrent runs).  `count` instances,
+ * each with its own grid, guides and partition; instances with identical
+ * grids form a group that shares tables and whose passes run as one
+ * persistent launch over all of the group's fields.  Groups run concurrently
+ * on library-owned streams, ordered after everything already enqueued on
+ * `hip_stream` and before anything enqueued there later.
+ * ssf_batch_run: nsteps real-time steps of every field psi[i] (host array of
+ * device pointers, complex64/complex128 per dtype, in place), the steps in
+ * chunks of `chunk` captured once in a HIP graph and replayed; then, if
+ * obs_dev != NULL, obs_dev[i] = observation of field i (populations give
+ * the transfer fidelity).  ssf_batch_tune runs ssf_tune on every group.
+ * Creation copies the guide descriptions (allocates); runs allocate nothing
+ * after the first with a given (dt, chunk). */
+typedef struct ssf_batch ssf_batch;
+ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf_ctap_desc* guides,
+                            const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
+                            ssf_batch** out);
+ssf_status ssf_batch_run(ssf_batch* b, void* const* psi, int64_t nsteps, double dt, int64_t chunk,
+                         ssf_obs* obs_dev);
+ssf_status ssf_batch_tune(ssf_batch* b, int32_t reps);
+/* Number of groups and the group of each instance (group_of[count], may be NULL). */
+ssf_status ssf_batch_info(ssf_batch* b, int32_t* ngroups, int32_t* group_of);
+ssf_status ssf_batch_destroy(ssf_batch* b);
 
 /* Host helper: clamped uniform cubic B-spline basis on [a, b] with M >= 4
  * functions evaluated at z[0..nz-1]; B_out is (nz, M) row-major, FP64. */

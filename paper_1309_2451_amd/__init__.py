@@ -20,7 +20,7 @@ import numpy as np
 from . import _ssf
 from ._ssf import OBS_DTYPE, SSF_C64, SSF_C128, SSF_IMAG, SSF_REAL, SSFError
 
-__all__ = ["Solver", "SSFError", "OBS_DTYPE", "supported_length", "bspline_basis", "load"]
+__all__ = ["Solver", "Batch", "SSFError", "OBS_DTYPE", "supported_length", "bspline_basis", "load"]
 
 
 def load():
@@ -244,3 +244,91 @@ class Solver:
 
     def sync(self):
         _ssf.call("ssf_sync", self.h)
+
+
+class Batch:
+    """Many independent instances (an ssf_batch): instance i has its own grid
+    n[i], lo[i], hi[i], guides (v0[i], sigma[i], xc[i] of shape (3, Nz_i)) and
+    partition (x_lo[i], x_hi[i]).  Instances with equal grids share tables and
+    are stepped together by one persistent launch per pass; the groups run
+    concurrently.  Fields are a list of tensors (Nz_i, Ny_i, Nx_i)."""
+
+    def __init__(self, grids, guides, x_lo, x_hi, dtype="c64", device=None):
+        torch = _torch()
+        self.torch = torch
+        self.count = len(grids)
+        if not (len(guides) == len(x_lo) == len(x_hi) == self.count) or self.count < 1:
+            raise ValueError("grids, guides, x_lo, x_hi must have one entry per instance")
+        self.dtype = {"c64": SSF_C64, "c128": SSF_C128}[dtype]
+        self.tdtype = torch.complex64 if self.dtype == SSF_C64 else torch.complex128
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        gd = (_ssf.ssf_grid_desc * self.count)()
+        cd = (_ssf.ssf_ctap_desc * self.count)()
+        self._xc = []
+        self.shapes = []
+        for i, ((n, lo, hi), (v0, sigma, xc)) in enumerate(zip(grids, guides)):
+            for a in range(3):
+                gd[i].n[a], gd[i].lo[a], gd[i].hi[a] = int(n[a]), float(lo[a]), float(hi[a])
+            xc = np.ascontiguousarray(xc, dtype=np.float64)
+            if xc.ndim != 2 or xc.shape[1] != int(n[2]) or not 1 <= xc.shape[0] <= 3:
+                raise ValueError("instance %d: xc must be (nguides, Nz)" % i)
+            cd[i].nguides = xc.shape[0]
+            for g in range(xc.shape[0]):
+                cd[i].v0[g] = float(v0[g])
+                cd[i].sigma[g] = float(sigma[g])
+            cd[i].xc = xc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self._xc.append(xc)
+            self.shapes.append((int(n[2]), int(n[1]), int(n[0])))
+        lo_a = np.ascontiguousarray(x_lo, dtype=np.float64)
+        hi_a = np.ascontiguousarray(x_hi, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _ssf.call("ssf_batch_create", self.count, gd, cd, lo_a.ctypes.data_as(dp), hi_a.ctypes.data_as(dp),
+                      self.dtype, ctypes.c_void_p(stream), ctypes.byref(h))
+        self.h = h
+        self._ptrs = (ctypes.c_void_p * self.count)()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _ssf.call("ssf_batch_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def groups(self):
+        """(number of groups, group index of each instance)."""
+        ng = ctypes.c_int32()
+        gof = np.zeros(self.count, dtype=np.int32)
+        _ssf.call("ssf_batch_info", self.h, ctypes.byref(ng), ctypes.c_void_p(gof.ctypes.data))
+        return int(ng.value), gof
+
+    def empty(self):
+        return [self.torch.empty(s, dtype=self.tdtype, device=self.device) for s in self.shapes]
+
+    def obs_buffer(self):
+        return self.torch.zeros(self.count * OBS_DTYPE.itemsize, dtype=self.torch.uint8, device=self.device)
+
+    def tune(self, reps=5):
+        _ssf.call("ssf_batch_tune", self.h, int(reps))
+
+    def run(self, fields, nsteps, dt, chunk=50, obs_buf=None):
+        if len(fields) != self.count:
+            raise ValueError("need one field per instance")
+        for i, (t, s) in enumerate(zip(fields, self.shapes)):
+            if t.dtype != self.tdtype or tuple(t.shape) != s or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("field %d must be a contiguous %s tensor of shape %s on %s"
+                                 % (i, self.tdtype, s, self.device))
+            self._ptrs[i] = t.data_ptr()
+        ob = ctypes.c_void_p(obs_buf.data_ptr()) if obs_buf is not None else ctypes.c_void_p(0)
+        _ssf.call("ssf_batch_run", self.h, self._ptrs, int(nsteps), float(dt), int(chunk), ob)
+
+    def read_obs(self, buf):
+        """Observation records of the last run (host, OBS_DTYPE)."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=OBS_DTYPE).copy()

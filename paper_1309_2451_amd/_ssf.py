@@ -34,7 +34,8 @@ EXPORTS = (
     "ssf_set_partition", "ssf_set_fusion", "ssf_set_timing", "ssf_timing_read",
     "ssf_tune", "ssf_set_tiles", "ssf_get_tiles", "ssf_step", "ssf_fft", "ssf_observables",
     "ssf_obs_read", "ssf_sync", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
-    "ssf_adjoint_segment", "ssf_profile_grad", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
+    "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
+    "ssf_batch_info", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
 )
 
 
@@ -109,6 +110,11 @@ def load():
         "ssf_adjoint_init": ([hp, vp, vp], i32),
         "ssf_adjoint_segment": ([hp, vp, vp, i64, dbl, vp], i32),
         "ssf_profile_grad": ([hp, vp, i32, vp, i32, vp], i32),
+        "ssf_batch_create": ([i32, vp, vp, dp, dp, i32, vp, ctypes.POINTER(hp)], i32),
+        "ssf_batch_run": ([hp, vp, i64, dbl, i64, vp], i32),
+        "ssf_batch_tune": ([hp, i32], i32),
+        "ssf_batch_info": ([hp, ctypes.POINTER(i32), vp], i32),
+        "ssf_batch_destroy": ([hp], i32),
         "ssf_bspline_basis": ([i32, dbl, dbl, dp, i32, dp], i32),
         "ssf_status_string": ([i32], ctypes.c_char_p),
         "ssf_last_error": ([], ctypes.c_char_p),

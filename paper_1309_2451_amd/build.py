@@ -49,31 +49,35 @@ def _stale(obj, deps):
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def build(jobs: int | None = None, verbose: bool = False, force: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = False, force: bool = True, defines=(), out: str | None = None,
+          build_dir: str | None = None) -> str:
     """Compile every translation unit (force=True) or only those older than
     their sources (force=False), then link libssf.so."""
-    os.makedirs(BUILD, exist_ok=True)
+    bdir = build_dir or BUILD
+    lib = out or LIB
+    os.makedirs(bdir, exist_ok=True)
+    extra = ["-D" + d for d in defines]
     hdrs = [os.path.join(CSRC, f) for f in ("ssf_internal.hpp", "ssf_pass.hpp")]
     hdrs.append(os.path.join(os.path.dirname(HERE), "include", "ssf.h"))
     jobs = jobs or int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))
     jobs = max(1, min(jobs, 16))
     tasks = []
     for n in lengths():
-        obj = os.path.join(BUILD, "ssf_kernels_%d.o" % n)
-        tasks.append([HIPCC] + FLAGS + ["-DSSF_N=%d" % n, "-c",
+        obj = os.path.join(bdir, "ssf_kernels_%d.o" % n)
+        tasks.append([HIPCC] + FLAGS + extra + ["-DSSF_N=%d" % n, "-c",
                                         os.path.join(CSRC, "ssf_kernels.hip"), "-o", obj])
-    rt_obj = os.path.join(BUILD, "ssf_runtime.o")
-    tasks.append([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "ssf_runtime.hip"), "-o", rt_obj])
+    rt_obj = os.path.join(bdir, "ssf_runtime.o")
+    tasks.append([HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, "ssf_runtime.hip"), "-o", rt_obj])
     todo = [t for t in tasks if force or _stale(t[-1], hdrs + [t[-3]])]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, todo):
             if verbose and out.strip():
                 print(out)
     objs = [t[-1] for t in tasks]
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
@@ -81,6 +85,9 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("-v", action="store_true")
     ap.add_argument("--incremental", action="store_true", help="only recompile stale objects")
+    ap.add_argument("-D", dest="defines", action="append", default=[], help="extra preprocessor define")
+    ap.add_argument("--out", default=None, help="output library path (default: in the package)")
+    ap.add_argument("--build-dir", default=None)
     a = ap.parse_args()
-    print(build(a.jobs, a.v, force=not a.incremental))
+    print(build(a.jobs, a.v, force=not a.incremental, defines=a.defines, out=a.out, build_dir=a.build_dir))
     sys.exit(0)

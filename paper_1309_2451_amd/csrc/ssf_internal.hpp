@@ -29,6 +29,15 @@ enum PassKind : int {
   NUM_PASS_KINDS = 6
 };
 
+// One instance of a batched launch: its field and its guide tables
+// (A | D | B, MAX_GUIDES planes each, as for a single handle).
+struct InstDesc {
+  const void* in;
+  void* out;
+  const double* ctap;
+  int ix_lo, ix_hi;        // guide partition of this instance (observations)
+};
+
 struct PassArgs {
   const void* in;          // storage in  (float2 or double2)
   void* out;               // storage out (may equal in)
@@ -55,6 +64,9 @@ struct PassArgs {
   double kfac[3];          // 2 pi / L per axis
   int ix_lo, ix_hi;        // P1: ix < ix_lo, P3: ix > ix_hi, P2 otherwise
   int tiles_x, tiles_y;    // tile grid (set by the launcher); partial sums are per tile
+  int small_phase;         // 1: |V cmid| <= pi/4 everywhere (no argument reduction needed)
+  const InstDesc* inst;    // batched launch: ninst instances of this grid (nullptr: single field)
+  int ninst;
 };
 
 // Tile geometry and launcher for one transform length and one storage type.
@@ -64,7 +76,7 @@ struct PassShape {
 };
 
 // Strided tile variants (chosen per axis by the autotuner): 0 = px columns of
-// 128 B of storage; 1 = half as many columns, twice the values per thread.
+// 128 B of storage; 1 = half as many columns (half the workgroup and LDS).
 constexpr int NUM_STRIDED_VARIANTS = 2;
 
 struct KernelSet {

@@ -74,6 +74,17 @@ template <class PL, bool REV> struct Order {
   }
 };
 
+// Build-time tuning switches (defaults are the measured best).
+#ifndef SSF_TW_FULL
+#define SSF_TW_FULL 0          // 1: load every twiddle power from LDS
+#endif
+#ifndef SSF_CR_SHIFT
+#define SSF_CR_SHIFT 0         // x-pass rows per workgroup scaled by 2^shift
+#endif
+#ifndef SSF_STRIDED_MAXWG
+#define SSF_STRIDED_MAXWG 512  // largest y/z workgroup
+#endif
+
 // Tile shapes.  LDS holds P pencils of N FP64 complex values.
 constexpr int LDS_CAP_ELEMS = 8192;       // 128 KiB of double2
 template <int N> struct Shape {
@@ -92,19 +103,22 @@ template <int N> struct Shape {
   }
   static constexpr int sm0(int dt) {               // variant-0 values-per-thread multiplier
     int em = 1;
-    while (sx0(dt) * so(dt) * N / (E * em) > 512) em *= 2;
+    while (sx0(dt) * so(dt) * N / (E * em) > SSF_STRIDED_MAXWG) em *= 2;
     return em;
   }
-  // variant 1 (half-width tile, twice the values per thread) exists when the
-  // doubled value count still divides N
-  static constexpr bool v1(int dt) { return sx0(dt) > 1 && N % (E * sm0(dt) * 2) == 0; }
+  // variant 1: half-width tile with the same values per thread, i.e. half
+  // the workgroup and half the LDS, so twice as many workgroups share a CU
+  static constexpr bool v1(int dt) { return sx0(dt) > 1; }
   static constexpr int sx(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sx0(dt) / 2 : sx0(dt); }
-  static constexpr int sm(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sm0(dt) * 2 : sm0(dt); }
+  static constexpr int sm(int dt, int var = 0) { return sm0(dt); }
   static constexpr int ldrow() { return N + N / 8 + (N >= 8 ? 0 : 0); }
   static constexpr int cr() {              // contiguous rows per workgroup
     int rows = 256 * E / N;
+    if (SSF_CR_SHIFT > 0) rows <<= SSF_CR_SHIFT;
+    if (SSF_CR_SHIFT < 0) rows >>= -SSF_CR_SHIFT;
     if (rows < 1) rows = 1;
     while (rows > 1 && rows * ldrow() > 4096) rows /= 2;
+    while (rows > 1 && rows * N / E > 1024) rows /= 2;
     return rows;
   }
 };
@@ -295,6 +309,20 @@ __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   *s = sgn_s * (swap ? cr : sr);
   *c = sgn_c * (swap ? sr : cr);
 }
+// exp(-i theta) for |theta| <= pi/4 (no reduction needed): Taylor series of
+// sin to degree 15 and of cos to degree 16, truncation error below 5e-17.
+__device__ __forceinline__ double2 phase_small(double r) {
+  const double r2 = r * r;
+  double ps = SINCOS_C[1];
+#pragma unroll
+  for (int k = 2; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
+  const double sr = fma(ps * r2, r, r);
+  double pc = SINCOS_C[9];
+#pragma unroll
+  for (int k = 10; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
+  const double cr = fma(-pc, r2, 1.0);
+  return make_double2(cr, -sr);
+}
 // exp(-i theta)
 __device__ __forceinline__ double2 phase_rt(double theta) {
   double s, c;
@@ -350,6 +378,21 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double* dst, double
 // ---------------------------------------------------------------------------
 // The pass kernel.
 // ---------------------------------------------------------------------------
+// Ordering of LDS writes and reads between Stockham stages: a workgroup
+// barrier, or -- when every row lives in one wave -- a wavefront-scope
+// release/acquire fence around a wave barrier (LDS operations of one wave
+// complete in order; the fences also stop the compiler from moving them).
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <typename S, int N, int PX, int PO, bool CONTIG, int EM = 1>
 struct PassGeom {
   using PL = Plan<N>;
@@ -362,10 +405,29 @@ struct PassGeom {
   static constexpr int LDROW = Shape<N>::ldrow();
   static constexpr int LDS = PL::S > 1 ? (CONTIG ? P * LDROW : P * N) : 1;
 
-  // butterfly g of a radix-r stage -> (pencil b, butterfly i within the pencil)
-  template <int r> __device__ static __forceinline__ void map(int g, int& b, int& i) {
-    if constexpr (CONTIG) { i = g % (N / r); b = g / (N / r); }
-    else { b = g % P; i = g / P; }
+  // x passes whose rows fit in a wave (64 E a multiple of N, whole waves per
+  // workgroup): each wave owns PPW whole rows in every stage layout, so the
+  // LDS exchanges between stages stay inside the wave and need no workgroup
+  // barrier.
+  static constexpr int PPW = CONTIG ? (64 * E) / N : 0;
+  static constexpr bool WAVELOCAL = CONTIG && (64 * E) % N == 0 && PPW >= 1 && WG % 64 == 0 && P % PPW == 0;
+
+  // butterfly u (0 <= u < E/r) of this thread in a radix-r stage ->
+  // (pencil b of the tile, butterfly i within the pencil)
+  template <int r> __device__ static __forceinline__ void map(int u, int& b, int& i) {
+    if constexpr (WAVELOCAL) {
+      const int q = (threadIdx.x & 63) + 64 * u;
+      i = q % (N / r);
+      b = (threadIdx.x >> 6) * PPW + q / (N / r);
+    } else if constexpr (CONTIG) {
+      const int g = threadIdx.x + WG * u;
+      i = g % (N / r);
+      b = g / (N / r);
+    } else {
+      const int g = threadIdx.x + WG * u;
+      b = g % P;
+      i = g / P;
+    }
   }
   __device__ static __forceinline__ int lidx(int b, int n) {
     if constexpr (CONTIG) return b * LDROW + n + (n >> 3);
@@ -381,7 +443,7 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2*
 #pragma unroll
   for (int u = 0; u < E / r; ++u) {
     int b, i;
-    G::template map<r>(threadIdx.x + G::WG * u, b, i);
+    G::template map<r>(u, b, i);
     double2* x = &v[u * r];
     if constexpr (p > 1) {
       // input m is multiplied by w^m, w = exp(sign 2 pi i k / (p r)) = W[k N/(p r)].
@@ -390,6 +452,13 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2*
       const int k = i % p;
       constexpr int step = N / (p * r);
       double2 w[r];
+#if SSF_TW_FULL
+#pragma unroll
+      for (int m = 1; m < r; ++m) {
+        w[m] = tw[m * k * step];
+        if constexpr (INV) w[m].y = -w[m].y;
+      }
+#else
 #pragma unroll
       for (int m = 1; m < r; m <<= 1) {
         w[m] = tw[m * k * step];
@@ -400,6 +469,7 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2*
         const int hp = 1 << (31 - __builtin_clz(m));
         if (hp != m) w[m] = cmul(w[hp], w[m - hp]);
       }
+#endif
 #pragma unroll
       for (int m = 1; m < r; ++m) x[m] = cmul(x[m], w[m]);
     }
@@ -417,21 +487,21 @@ __device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds) {
 #pragma unroll
   for (int u = 0; u < E / r1; ++u) {
     int b, i;
-    G::template map<r1>(threadIdx.x + G::WG * u, b, i);
+    G::template map<r1>(u, b, i);
     const int k = i % p1;
     const int j = (i - k) * r1 + k;
 #pragma unroll
     for (int q = 0; q < r1; ++q) lds[G::lidx(b, j + q * p1)] = v[u * r1 + q];
   }
-  __syncthreads();
+  lds_sync<G::WAVELOCAL>();
 #pragma unroll
   for (int u = 0; u < E / r2; ++u) {
     int b, i;
-    G::template map<r2>(threadIdx.x + G::WG * u, b, i);
+    G::template map<r2>(u, b, i);
 #pragma unroll
     for (int m = 0; m < r2; ++m) v[u * r2 + m] = lds[G::lidx(b, i + m * (N / r2))];
   }
-  __syncthreads();
+  lds_sync<G::WAVELOCAL>();
 }
 
 // All stages of one transform direction; v holds the inputs of stage 0 on
@@ -479,7 +549,7 @@ __device__ __forceinline__ void pencils(Pen<G, r>& p, const PassArgs& a, int t) 
 #pragma unroll
   for (int u = 0; u < Pen<G, r>::U; ++u) {
     int b, i;
-    G::template map<r>(threadIdx.x + G::WG * u, b, i);
+    G::template map<r>(u, b, i);
     p.i[u] = i;
     if constexpr (G::CONTIGUOUS) {
       const int y = t0 * G::P + b;
@@ -600,24 +670,26 @@ pass_kernel(PassArgs a) {
   __shared__ double red[((WG + 63) / 64) * NRED_OBS];
   extern __shared__ double s_dyn[];                                // x passes: B_g(y), MAX_GUIDES * ny
 
-  const int ntiles = a.tiles_x * a.tiles_y;
+  // tiles of one field; a batched launch covers ninst fields of this grid,
+  // instance-major (global tile tg = instance * tpi + local tile)
+  const int tpi = a.tiles_x * a.tiles_y;
+  const int ntiles = tpi * (a.ninst > 0 ? a.ninst : 1);
   const int chunk = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
   const int tbeg = (int)blockIdx.x * chunk;
   const int tend = min(ntiles, tbeg + chunk);
   if (tbeg >= tend) return;                                        // whole workgroup
 
-  const S* __restrict__ in = (const S*)a.in;
-  S* __restrict__ out = (S*)a.out;
   const bool ctap = CONTIG && a.vkind == V_CTAP;
+  const long long gplane = (long long)MAX_GUIDES * a.nz * a.nx;    // one guide table (A or D)
+  auto field_in = [&](int k) -> const S* { return a.ninst > 0 ? (const S*)a.inst[k].in : (const S*)a.in; };
+  auto field_out = [&](int k) -> S* { return a.ninst > 0 ? (S*)a.inst[k].out : (S*)a.out; };
+  auto guideA = [&](int k) -> const double* { return a.ninst > 0 ? a.inst[k].ctap : a.ctapA; };
+  auto guideB = [&](int k) -> const double* { return a.ninst > 0 ? a.inst[k].ctap + 2 * gplane : a.ctapB; };
 
-  // tables into LDS (once per workgroup)
+  // tables into LDS (once per workgroup; the guide B table again when the instance changes)
   for (int j = threadIdx.x; j < N; j += WG) {
     s_tw[j] = a.tw[j];
     if constexpr (KZ) s_kz[j] = a.kt[2][j];
-  }
-  if constexpr (CONTIG) {
-    if (ctap)
-      for (int j = threadIdx.x; j < MAX_GUIDES * a.ny; j += WG) s_dyn[j] = a.ctapB[j];
   }
   const double pre_scale = (CONTIG && (a.pre & PRE_SCALE)) ? *a.scale : 1.0;
   __syncthreads();
@@ -629,7 +701,10 @@ pass_kernel(PassArgs a) {
   // kinetic factor kx(x) ky(y) per thread and tile.
   S raw[E];
   double2 kx_n, ky_n;
-  auto load_tile = [&](int t) {
+  auto load_tile = [&](int tg) {
+    const int k = a.ninst > 0 ? tg / tpi : 0;
+    const int t = tg - k * tpi;
+    const S* __restrict__ in = field_in(k);
     Pen<G, r0> p;
     pencils(p, a, t);
 #pragma unroll
@@ -653,28 +728,37 @@ pass_kernel(PassArgs a) {
   const bool prefetch = LEAN || !(CONTIG && ((a.pre & PRE_ADJ) || (a.post & POST_ADJ) ||
                                              (!ctap && a.vkind != V_NONE)));
 
-  int plane = -1;
+  int plane = -1, binst = -1;
   if (prefetch) load_tile(tbeg);
-  for (int t = tbeg; t < tend; ++t) {
+  for (int tg = tbeg; tg < tend; ++tg) {
+    const int k = a.ninst > 0 ? tg / tpi : 0;
+    const int t = tg - k * tpi;
     const int t1 = t / a.tiles_x;
+    S* __restrict__ out = field_out(k);
     if constexpr (CONTIG) {
-      if (ctap && t1 != plane) {
-        // guide tables A_g(x, z) of this plane into LDS
+      if (ctap && (k != binst || t1 != plane)) {
+        // guide tables of this plane (A_g(x, z)) and instance (B_g(y)) into LDS
         __syncthreads();
         const long long pl = (long long)a.nz * a.nx;
+        const double* A = guideA(k);
         for (int j = threadIdx.x; j < MAX_GUIDES * N; j += WG)
-          s_A[j] = a.ctapA[(j / N) * pl + (long long)t1 * a.nx + (j % N)];
+          s_A[j] = A[(j / N) * pl + (long long)t1 * a.nx + (j % N)];
+        if (k != binst) {
+          const double* B = guideB(k);
+          for (int j = threadIdx.x; j < MAX_GUIDES * a.ny; j += WG) s_dyn[j] = B[j];
+        }
         __syncthreads();
         plane = t1;
+        binst = k;
       }
     }
-    if (!prefetch) load_tile(t);
+    if (!prefetch) load_tile(tg);
     double2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = make_double2((double)raw[e].x, (double)raw[e].y);
     double2 kxy = make_double2(1.0, 0.0);
     if constexpr (KZ) kxy = cmul(kx_n, ky_n);
-    if (prefetch && t + 1 < tend) load_tile(t + 1);
+    if (prefetch && tg + 1 < tend) load_tile(tg + 1);
 
     double acc[NRED_OBS];
 #pragma unroll
@@ -720,8 +804,13 @@ pass_kernel(PassArgs a) {
                 V[u * rm + m] = ctap ? -(s_A[x] * b0 + s_A[N + x] * b1 + s_A[2 * N + x] * b2) : 0.0;
               }
             }
+            if (a.small_phase) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt(V[e] * a.cmid));
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_small(V[e] * a.cmid));
+            } else {
+#pragma unroll
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt(V[e] * a.cmid));
+            }
           } else {
             potentials<G, rm>(a, s_A, s_dyn, p, t1, V);
 #pragma unroll
@@ -733,7 +822,7 @@ pass_kernel(PassArgs a) {
 #pragma unroll
           for (int u = 0; u < UM; ++u) {
             int b, i;
-            G::template map<rm>(threadIdx.x + WG * u, b, i);
+            G::template map<rm>(u, b, i);
 #pragma unroll
             for (int q = 0; q < rm; ++q) v[u * rm + q] = cmul(v[u * rm + q], cmul(kxy, s_kz[i + q * (N / rm)]));
           }
@@ -813,7 +902,7 @@ pass_kernel(PassArgs a) {
 
     if constexpr (!LEAN) {
       if ((a.post & (POST_OBS | POST_ADJ | POST_KIN)) || (a.pre & PRE_ADJ))
-        block_sum<WG, NRED_OBS>(acc, a.partials + (long long)t * NRED_OBS, red);
+        block_sum<WG, NRED_OBS>(acc, a.partials + (long long)tg * NRED_OBS, red);
     }
   }
 }
@@ -845,7 +934,7 @@ hipError_t launch_persistent(K kernel, int wg, size_t dyn, PassArgs a, dim3 tile
   }
   a.tiles_x = (int)tiles.x;
   a.tiles_y = (int)tiles.y;
-  const long long ntiles = (long long)tiles.x * tiles.y;
+  const long long ntiles = (long long)tiles.x * tiles.y * (a.ninst > 0 ? a.ninst : 1);
   long long grid = (long long)occ * device_cus();
   if (grid > ntiles) grid = ntiles;
   if (grid < 1) grid = 1;

@@ -208,6 +208,61 @@ __global__ void mask_kernel(const S* psi, S* lam, long long n, int nx, int ix_hi
   }
 }
 
+// Observations of the ninst fields of a batched group: block (y tile of `rows`
+// rows, plane z, instance k); partials are instance-major.
+template <typename S>
+__global__ void __launch_bounds__(256) obs_reduce_batch(PassArgs a, int rows) {
+  __shared__ double red[4 * 8];
+  const int k = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * rows;
+  const ssf::InstDesc d = a.inst[k];
+  const S* in = (const S*)d.in;
+  const long long pl = (long long)a.nz * a.nx;
+  const long long gplane = (long long)ssf::MAX_GUIDES * pl;
+  const double* A = d.ctap;
+  const double* B = d.ctap + 2 * gplane;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int e = threadIdx.x; e < rows * a.nx; e += 256) {
+    const int y = y0 + e / a.nx, x = e % a.nx;
+    if (y >= a.ny) break;
+    const double2 v = ssf::ld2(in + ((long long)z * a.ny + y) * a.nx + x);
+    const double rho = v.x * v.x + v.y * v.y;
+    const long long o = (long long)z * a.nx + x;
+    const double V = -(A[o] * B[y] + A[pl + o] * B[a.ny + y] + A[2 * pl + o] * B[2 * a.ny + y]);
+    acc[0] += rho;
+    acc[1] += (a.lo[0] + x * a.d[0]) * rho;
+    acc[2] += (a.lo[1] + y * a.d[1]) * rho;
+    acc[3] += (a.lo[2] + z * a.d[2]) * rho;
+    if (x < d.ix_lo) acc[4] += rho;
+    else if (x > d.ix_hi) acc[6] += rho;
+    else acc[5] += rho;
+    acc[7] += V * rho;
+  }
+  ssf::block_sum<256, 8>(acc, a.partials + (((long long)k * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 8, red);
+}
+
+// Block k: fixed-order sum of instance k's nblk partials -> obs[slot[k]].
+__global__ void __launch_bounds__(256) obs_finalize_batch(const double* partials, long long nblk, double dv,
+                                                          ssf_obs* obs, const int* slot, long long step) {
+  __shared__ double sh[8 * 256];
+  double s[8];
+  sum_partials<8>(partials + (long long)blockIdx.x * nblk * 8, nblk, s, sh);
+  if (threadIdx.x != 0) return;
+  ssf_obs o;
+  o.norm = s[0] * dv;
+  o.mean[0] = s[1] * dv;
+  o.mean[1] = s[2] * dv;
+  o.mean[2] = s[3] * dv;
+  o.pop[0] = s[4] * dv;
+  o.pop[1] = s[5] * dv;
+  o.pop[2] = s[6] * dv;
+  o.epot = s[7] * dv;
+  o.energy = 0.0;
+  o.step = step;
+  o.flags = isfinite(o.norm) ? 0 : 1;
+  o.reserved = 0;
+  obs[slot[blockIdx.x]] = o;
+}
+
 // ---------------------------------------------------------------------------
 // Handle.
 // ---------------------------------------------------------------------------
@@ -239,6 +294,7 @@ struct ssf_handle {
   const void* vtab = nullptr;
   double* ctap = nullptr;              // A | D | B
   int nguides = 0;
+  double vmax = 0.0;                   // bound on |V| for the guide potential (sum of |v0|)
   int ix_lo = -1, ix_hi = 1 << 30;     // default: everything in P2
   int fuse = 1;
   int var[3] = {0, 0, 0};              // strided tile variant per axis (autotuned)
@@ -255,6 +311,45 @@ struct ssf_handle {
 namespace {
 
 long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+// Guide tables on the host, FP64: A_g(x, z), D_g(x, z) = A_g (x - xc_g)/s_g^2
+// and B_g(y) for MAX_GUIDES guides (unused ones zero), the layout the pass
+// kernels read.
+void ctap_tables(const ssf_handle* h, const ssf_ctap_desc* d, std::vector<double>& tab) {
+  // The kernels always evaluate MAX_GUIDES guides: unused ones get zero tables.
+  const int nx = h->n[0], ny = h->n[1], nz = h->n[2], ng = d->nguides;
+  const long long plane = (long long)ssf::MAX_GUIDES * nz * nx;
+  tab.assign(2 * plane + (long long)ssf::MAX_GUIDES * ny, 0.0);
+  for (int g = 0; g < ng; ++g) {
+    const double s2 = d->sigma[g] * d->sigma[g];
+    for (int z = 0; z < nz; ++z) {
+      const double xc = d->xc[(long long)g * nz + z];
+      for (int x = 0; x < nx; ++x) {
+        const double dx = h->lo[0] + x * h->d[0] - xc;
+        const double A = d->v0[g] * std::exp(-dx * dx / (2.0 * s2));
+        tab[((long long)g * nz + z) * nx + x] = A;
+        tab[plane + ((long long)g * nz + z) * nx + x] = A * dx / s2;
+      }
+    }
+    for (int y = 0; y < ny; ++y) {
+      const double yc = h->lo[1] + y * h->d[1];
+      tab[2 * plane + (long long)g * ny + y] = std::exp(-yc * yc / (2.0 * s2));
+    }
+  }
+}
+
+// Partition of x into guide regions as integer bounds: P1 for x_i < x_lo,
+// P3 for x_i > x_hi, with x_i = lo + i d (the expression the kernels use).
+void partition_indices(const ssf_handle* h, double x_lo, double x_hi, int* ilo, int* ihi) {
+  int a = 0;
+  while (a < h->n[0] && h->lo[0] + a * h->d[0] < x_lo) ++a;
+  int b = h->n[0] - 1;
+  while (b >= 0 && h->lo[0] + b * h->d[0] > x_hi) --b;
+  *ilo = a;
+  *ihi = b;
+}
+
+
 
 // Grid of one pass kind over the handle's field.
 dim3 pass_grid(const ssf_handle* h, int axis, int variant = -1) {
@@ -656,30 +751,14 @@ ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d) {
   if (d->nguides < 1 || d->nguides > ssf::MAX_GUIDES) return fail(SSF_E_INVALID, "nguides must be 1..3");
   for (int g = 0; g < d->nguides; ++g)
     if (!(d->sigma[g] > 0.0) || !std::isfinite(d->v0[g])) return fail(SSF_E_INVALID, "sigma must be > 0, v0 finite");
-  // The kernels always evaluate MAX_GUIDES guides: unused ones get zero tables.
-  const int nx = h->n[0], ny = h->n[1], nz = h->n[2], ng = d->nguides;
-  const long long plane = (long long)ssf::MAX_GUIDES * nz * nx;
-  std::vector<double> tab(2 * plane + (long long)ssf::MAX_GUIDES * ny, 0.0);
-  for (int g = 0; g < ng; ++g) {
-    const double s2 = d->sigma[g] * d->sigma[g];
-    for (int z = 0; z < nz; ++z) {
-      const double xc = d->xc[(long long)g * nz + z];
-      for (int x = 0; x < nx; ++x) {
-        const double dx = h->lo[0] + x * h->d[0] - xc;
-        const double A = d->v0[g] * std::exp(-dx * dx / (2.0 * s2));
-        tab[((long long)g * nz + z) * nx + x] = A;
-        tab[plane + ((long long)g * nz + z) * nx + x] = A * dx / s2;
-      }
-    }
-    for (int y = 0; y < ny; ++y) {
-      const double yc = h->lo[1] + y * h->d[1];
-      tab[2 * plane + (long long)g * ny + y] = std::exp(-yc * yc / (2.0 * s2));
-    }
-  }
+  std::vector<double> tab;
+  ctap_tables(h, d, tab);
   if (h->ctap) { HIP_TRY(hipStreamSynchronize(h->stream)); (void)hipFree(h->ctap); h->ctap = nullptr; }
   HIP_TRY(hipMalloc(&h->ctap, sizeof(double) * tab.size()));
   HIP_TRY(hipMemcpy(h->ctap, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
-  h->nguides = ng;
+  h->nguides = d->nguides;
+  h->vmax = 0.0;
+  for (int g = 0; g < d->nguides; ++g) h->vmax += std::fabs(d->v0[g]);
   h->vkind = ssf::V_CTAP;
   h->vtab = nullptr;
   return SSF_OK;
@@ -688,12 +767,8 @@ ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d) {
 ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi) {
   SSF_TRY(check_handle(h));
   if (!(x_lo <= x_hi)) return fail(SSF_E_INVALID, "partition needs x_lo <= x_hi");
-  // P1: x_i < x_lo, P3: x_i > x_hi with x_i = lo + i d (same FP64 expression as the coordinates)
-  int ilo = 0, ihi = h->n[0] - 1;
-  ilo = 0;
-  while (ilo < h->n[0] && h->lo[0] + ilo * h->d[0] < x_lo) ++ilo;   // first index not in P1
-  ihi = h->n[0] - 1;
-  while (ihi >= 0 && h->lo[0] + ihi * h->d[0] > x_hi) --ihi;        // last index not in P3
+  int ilo = 0, ihi = 0;
+  partition_indices(h, x_lo, x_hi, &ilo, &ihi);
   h->ix_lo = ilo;
   h->ix_hi = ihi;
   return SSF_OK;
@@ -753,6 +828,8 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
       am.mid = ssf::MID_VPHASE;
       am.cmid = dt;
       am.imag = imag;
+      // |V dt| <= pi/4 lets the phase skip its argument reduction
+      am.small_phase = (h->vkind == ssf::V_CTAP && h->vmax * std::fabs(dt) <= 0.78) || h->vkind == ssf::V_NONE;
       SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
     }
   }
@@ -941,6 +1018,326 @@ ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int
       if (m >= 0 && m < M) row[m] = Nl[r];
     }
   }
+  return SSF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched instances (parameter sweeps).  Instances with the same grid form a
+// group: one handle (twiddles, kinetic tables, tile choice), per-instance
+// guide tables and a device descriptor array.  Every pass of a step is one
+// persistent launch over all tiles of all instances of the group; groups run
+// concurrently on their own streams, and a chunk of steps is captured in a
+// HIP graph (fork/join over the group streams) that is replayed.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct BatchGroup {
+  ssf_handle* h = nullptr;
+  std::vector<int> members;            // global instance indices
+  ssf::InstDesc* d_inst = nullptr;     // device descriptors
+  std::vector<ssf::InstDesc> inst;     // host copy
+  int* d_slot = nullptr;               // device: members
+  std::vector<double*> ctap;           // per-instance guide tables (device)
+  double vmax = 0.0;
+  double* obs_part = nullptr;          // observation partials, instance-major
+  long long obs_blocks = 0;            // per instance
+  hipStream_t stream = nullptr;
+  hipEvent_t join = nullptr;
+};
+
+}  // namespace
+
+struct ssf_batch {
+  int count = 0, dtype = 0, device = 0;
+  hipStream_t user = nullptr, cap = nullptr;
+  hipEvent_t ev_start = nullptr, ev_fork = nullptr, ev_done = nullptr;
+  std::vector<BatchGroup> groups;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double graph_dt = 0.0;
+  int64_t graph_k = 0;
+  std::vector<const double2*> graph_kt;   // kinetic tables the graph reads
+};
+
+namespace {
+
+PassArgs batch_args(BatchGroup& G, int axis) {
+  PassArgs a = base_args(G.h, nullptr, nullptr, axis);
+  a.inst = G.d_inst;
+  a.ninst = (int)G.members.size();
+  a.vkind = ssf::V_CTAP;
+  a.nguides = ssf::MAX_GUIDES;
+  return a;
+}
+
+// k real-time Strang steps of every instance of the group (fused chain:
+// x forward with the half potential phase, k x (y, z, y) with the fused x
+// pass between steps, x inverse with the half phase).
+ssf_status batch_chunk(BatchGroup& G, int64_t k, double dt, const double2* kt) {
+  ssf_handle* h = G.h;
+  PassArgs ax = batch_args(G, 0);
+  ax.pre = ssf::PRE_VPHASE;
+  ax.cpre = 0.5 * dt;
+  SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
+  for (int64_t s = 1; s <= k; ++s) {
+    PassArgs ay = batch_args(G, 1);
+    SSF_TRY(launch(h, ssf::STRIDED_FWD, 1, ay));
+    PassArgs az = batch_args(G, 2);
+    az.mid = ssf::MID_KINETIC;
+    az.kt[0] = kt;
+    az.kt[1] = kt + h->n[0];
+    az.kt[2] = kt + h->n[0] + h->n[1];
+    SSF_TRY(launch(h, ssf::STRIDED_FUSED, 2, az));
+    SSF_TRY(launch(h, ssf::STRIDED_INV, 1, ay));
+    PassArgs am = batch_args(G, 0);
+    if (s < k) {
+      am.mid = ssf::MID_VPHASE;
+      am.cmid = dt;
+      am.small_phase = G.vmax * std::fabs(dt) <= 0.78 ? 1 : 0;
+      SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
+    } else {
+      am.post = ssf::POST_VPHASE;
+      am.cpost = 0.5 * dt;
+      SSF_TRY(launch(h, ssf::CONTIG_INV, 0, am));
+    }
+  }
+  return SSF_OK;
+}
+
+ssf_status batch_fork(ssf_batch* b) {
+  HIP_TRY(hipEventRecord(b->ev_fork, b->cap));
+  for (auto& G : b->groups) HIP_TRY(hipStreamWaitEvent(G.stream, b->ev_fork, 0));
+  return SSF_OK;
+}
+
+ssf_status batch_join(ssf_batch* b) {
+  for (auto& G : b->groups) {
+    HIP_TRY(hipEventRecord(G.join, G.stream));
+    HIP_TRY(hipStreamWaitEvent(b->cap, G.join, 0));
+  }
+  return SSF_OK;
+}
+
+ssf_status batch_chunks_all(ssf_batch* b, int64_t k, double dt, const std::vector<const double2*>& kts) {
+  SSF_TRY(batch_fork(b));
+  for (size_t i = 0; i < b->groups.size(); ++i) SSF_TRY(batch_chunk(b->groups[i], k, dt, kts[i]));
+  return batch_join(b);
+}
+
+void batch_free(ssf_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->cap) (void)hipStreamSynchronize(b->cap);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& G : b->groups) {
+    if (G.stream) (void)hipStreamSynchronize(G.stream);
+    for (double* c : G.ctap) if (c) (void)hipFree(c);
+    if (G.d_inst) (void)hipFree(G.d_inst);
+    if (G.d_slot) (void)hipFree(G.d_slot);
+    if (G.obs_part) (void)hipFree(G.obs_part);
+    if (G.join) (void)hipEventDestroy(G.join);
+    if (G.h) { G.h->stream = G.stream; (void)ssf_destroy(G.h); }
+    if (G.stream) (void)hipStreamDestroy(G.stream);
+  }
+  if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+bool same_grid(const ssf_grid_desc& a, const ssf_grid_desc& c) {
+  for (int q = 0; q < 3; ++q)
+    if (a.n[q] != c.n[q] || a.lo[q] != c.lo[q] || a.hi[q] != c.hi[q]) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf_ctap_desc* guides,
+                            const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
+                            ssf_batch** out) {
+  if (!out || count < 1 || !grids || !guides || !x_lo || !x_hi) return fail(SSF_E_INVALID, "bad batch arguments");
+  *out = nullptr;
+  ssf_batch* b = new ssf_batch();
+  b->count = count;
+  b->dtype = dtype;
+  b->user = (hipStream_t)hip_stream;
+  if (hipGetDevice(&b->device) != hipSuccess) { delete b; return fail(SSF_E_NODEVICE, "no HIP device"); }
+  auto bail = [&](ssf_status st) { batch_free(b); return st; };
+  std::vector<ssf_grid_desc> keys;
+  std::vector<int> gid(count);
+  for (int i = 0; i < count; ++i) {
+    int g = -1;
+    for (size_t j = 0; j < keys.size(); ++j)
+      if (same_grid(keys[j], grids[i])) { g = (int)j; break; }
+    if (g < 0) { keys.push_back(grids[i]); g = (int)keys.size() - 1; }
+    gid[i] = g;
+  }
+  b->groups.resize(keys.size());
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(SSF_E_DEVICE, "batch streams/events"));
+  for (size_t j = 0; j < keys.size(); ++j) {
+    BatchGroup& G = b->groups[j];
+    if (hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&G.join, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(SSF_E_DEVICE, "group stream/event"));
+    ssf_status st = ssf_create(&keys[j], dtype, G.stream, &G.h);
+    if (st != SSF_OK) return bail(st);
+  }
+  for (int i = 0; i < count; ++i) {
+    BatchGroup& G = b->groups[gid[i]];
+    const ssf_ctap_desc* d = &guides[i];
+    if (!d->xc || d->nguides < 1 || d->nguides > ssf::MAX_GUIDES) return bail(fail(SSF_E_INVALID, "bad guide description"));
+    for (int q = 0; q < d->nguides; ++q)
+      if (!(d->sigma[q] > 0.0) || !std::isfinite(d->v0[q])) return bail(fail(SSF_E_INVALID, "sigma must be > 0"));
+    if (!(x_lo[i] <= x_hi[i])) return bail(fail(SSF_E_INVALID, "partition needs x_lo <= x_hi"));
+    std::vector<double> tab;
+    ctap_tables(G.h, d, tab);
+    double* dev = nullptr;
+    if (hipMalloc(&dev, sizeof(double) * tab.size()) != hipSuccess) return bail(fail(SSF_E_NOMEM, "guide tables"));
+    G.ctap.push_back(dev);
+    if (hipMemcpy(dev, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(SSF_E_DEVICE, "guide table upload"));
+    double vm = 0.0;
+    for (int q = 0; q < d->nguides; ++q) vm += std::fabs(d->v0[q]);
+    G.vmax = std::max(G.vmax, vm);
+    ssf::InstDesc id;
+    id.in = nullptr;
+    id.out = nullptr;
+    id.ctap = dev;
+    partition_indices(G.h, x_lo[i], x_hi[i], &id.ix_lo, &id.ix_hi);
+    G.inst.push_back(id);
+    G.members.push_back(i);
+  }
+  for (auto& G : b->groups) {
+    const size_t n = G.members.size();
+    // the kernels index tiles of all instances of a launch with 32-bit integers
+    for (int ax = 0; ax < 3; ++ax)
+      for (int v = 0; v < (ax == 0 ? 1 : ssf::NUM_STRIDED_VARIANTS); ++v) {
+        const dim3 t = pass_grid(G.h, ax, ax == 0 ? -1 : v);
+        if ((long long)t.x * t.y * (long long)n >= (1LL << 31))
+          return bail(fail(SSF_E_UNSUPPORTED, "too many tiles in one batch group"));
+      }
+    const dim3 gx = pass_grid(G.h, 0);
+    G.obs_blocks = (long long)gx.x * gx.y;
+    if (hipMalloc(&G.d_inst, sizeof(ssf::InstDesc) * n) != hipSuccess ||
+        hipMalloc(&G.d_slot, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&G.obs_part, sizeof(double) * 8 * G.obs_blocks * n) != hipSuccess)
+      return bail(fail(SSF_E_NOMEM, "batch descriptors"));
+    if (hipMemcpy(G.d_slot, G.members.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(SSF_E_DEVICE, "batch slot upload"));
+  }
+  *out = b;
+  return SSF_OK;
+}
+
+ssf_status ssf_batch_destroy(ssf_batch* b) {
+  batch_free(b);
+  return SSF_OK;
+}
+
+ssf_status ssf_batch_info(ssf_batch* b, int32_t* ngroups, int32_t* group_of) {
+  if (!b || !ngroups) return fail(SSF_E_INVALID, "null batch");
+  *ngroups = (int32_t)b->groups.size();
+  if (group_of)
+    for (size_t j = 0; j < b->groups.size(); ++j)
+      for (int i : b->groups[j].members) group_of[i] = (int32_t)j;
+  return SSF_OK;
+}
+
+ssf_status ssf_batch_tune(ssf_batch* b, int32_t reps) {
+  if (!b) return fail(SSF_E_INVALID, "null batch");
+  HIP_TRY(hipSetDevice(b->device));
+  for (auto& G : b->groups) {
+    G.h->stream = G.stream;
+    SSF_TRY(ssf_tune(G.h, reps, nullptr, nullptr));
+  }
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return SSF_OK;
+}
+
+ssf_status ssf_batch_run(ssf_batch* b, void* const* psi, int64_t nsteps, double dt, int64_t chunk,
+                         ssf_obs* obs_dev) {
+  if (!b || !psi) return fail(SSF_E_INVALID, "null batch or field array");
+  if (nsteps < 0 || chunk < 1) return fail(SSF_E_INVALID, "need nsteps >= 0 and chunk >= 1");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
+  HIP_TRY(hipSetDevice(b->device));
+  const size_t esize = b->dtype == SSF_C64 ? 8 : 16;
+  // descriptors: field pointers of this call (uploaded only when they change)
+  for (auto& G : b->groups) {
+    bool changed = false;
+    for (size_t k = 0; k < G.members.size(); ++k) {
+      void* p = psi[G.members[k]];
+      if (!p || ((uintptr_t)p) % (esize / 2) != 0) return fail(SSF_E_INVALID, "field pointer null or misaligned");
+      if (G.inst[k].in != p) { G.inst[k].in = p; G.inst[k].out = p; changed = true; }
+    }
+    if (changed) {
+      HIP_TRY(hipStreamSynchronize(G.stream));
+      HIP_TRY(hipMemcpy(G.d_inst, G.inst.data(), sizeof(ssf::InstDesc) * G.inst.size(), hipMemcpyHostToDevice));
+    }
+  }
+  HIP_TRY(hipEventRecord(b->ev_start, b->user));
+  HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_start, 0));
+  // kinetic tables (built on the group streams, ordered after the fork)
+  std::vector<const double2*> kts(b->groups.size());
+  SSF_TRY(batch_fork(b));
+  for (size_t i = 0; i < b->groups.size(); ++i) {
+    b->groups[i].h->stream = b->groups[i].stream;
+    SSF_TRY(get_ktab(b->groups[i].h, dt, 0, &kts[i]));
+  }
+  SSF_TRY(batch_join(b));
+  // eager part: the remainder (or a first chunk), then graph replays of `chunk` steps
+  const int64_t q = nsteps / chunk, r = nsteps % chunk;
+  int64_t replays = q;
+  if (r > 0) SSF_TRY(batch_chunks_all(b, r, dt, kts));
+  else if (q > 0) { SSF_TRY(batch_chunks_all(b, chunk, dt, kts)); replays = q - 1; }
+  if (replays > 0) {
+    if (!b->exec || b->graph_dt != dt || b->graph_k != chunk || b->graph_kt != kts) {
+      if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+      if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+      HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+      ssf_status st = batch_chunks_all(b, chunk, dt, kts);
+      hipGraph_t gr = nullptr;
+      hipError_t ee = hipStreamEndCapture(b->cap, &gr);
+      if (st != SSF_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
+      if (ee != hipSuccess) return fail(SSF_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+      b->graph = gr;
+      HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_dt = dt;
+      b->graph_k = chunk;
+      b->graph_kt = kts;
+    }
+    for (int64_t i = 0; i < replays; ++i) HIP_TRY(hipGraphLaunch(b->exec, b->cap));
+  }
+  if (obs_dev) {
+    for (auto& G : b->groups) {
+      PassArgs a = batch_args(G, 0);
+      a.partials = G.obs_part;
+      const int rows = G.h->ks[0]->contig[G.h->dti].px;
+      const dim3 gx = pass_grid(G.h, 0);
+      const dim3 grid(gx.x, gx.y, (unsigned)G.members.size());
+      if (b->dtype == SSF_C64)
+        hipLaunchKernelGGL(obs_reduce_batch<float2>, grid, dim3(256), 0, b->cap, a, rows);
+      else
+        hipLaunchKernelGGL(obs_reduce_batch<double2>, grid, dim3(256), 0, b->cap, a, rows);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(obs_finalize_batch, dim3((unsigned)G.members.size()), dim3(256), 0, b->cap, G.obs_part,
+                         G.obs_blocks, G.h->dv, obs_dev, G.d_slot, (long long)nsteps);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  HIP_TRY(hipEventRecord(b->ev_done, b->cap));
+  HIP_TRY(hipStreamWaitEvent(b->user, b->ev_done, 0));
   return SSF_OK;
 }
 
