@@ -150,11 +150,33 @@ template <bool INV> __device__ __forceinline__ double2 mul_w8_3(double2 a) {
              : make_double2((a.y - a.x) * SQRT1_2, (-a.x - a.y) * SQRT1_2);
 }
 
-// Storage conversions.
-__device__ __forceinline__ double2 ld2(const float2* p) { float2 f = *p; return make_double2(f.x, f.y); }
-__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
-__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
-__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+// Storage conversions.  Field and table pointers may come from a batch
+// descriptor in memory rather than from the kernel arguments; the accesses
+// name the global address space explicitly so that they compile to global
+// (not flat) memory instructions, which do not tie up the LDS counter.
+#define SSF_GLOBAL __attribute__((address_space(1)))
+#define SSF_CONST __attribute__((address_space(4)))
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ldraw(const float2* p) {
+  const f2v_t t = *(const SSF_GLOBAL f2v_t*)p;
+  return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ double2 ldraw(const double2* p) {
+  const d2v_t t = *(const SSF_GLOBAL d2v_t*)p;
+  return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ double ldg(const double* p) { return *(const SSF_GLOBAL double*)p; }
+__device__ __forceinline__ double2 ld2(const float2* p) { const float2 f = ldraw(p); return make_double2(f.x, f.y); }
+__device__ __forceinline__ double2 ld2(const double2* p) { return ldraw(p); }
+__device__ __forceinline__ void st2(float2* p, double2 v) {
+  const f2v_t t = {(float)v.x, (float)v.y};
+  *(SSF_GLOBAL f2v_t*)p = t;
+}
+__device__ __forceinline__ void st2(double2* p, double2 v) {
+  const d2v_t t = {v.x, v.y};
+  *(SSF_GLOBAL d2v_t*)p = t;
+}
 // Value as it is after rounding to storage (for reductions that must see the stored field).
 __device__ __forceinline__ double2 rounded(double2 v, const float2*) { return make_double2((double)(float)v.x, (double)(float)v.y); }
 __device__ __forceinline__ double2 rounded(double2 v, const double2*) { return v; }
@@ -645,13 +667,16 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 
 // LEAN: only the mid op (potential phase from the guide tables in LDS, or
 // the kinetic factor); no pre/post ops, no reductions, no global tables.
 //
+// BATCH: the launch covers a.ninst fields of the same grid, each with its own
+// guide tables (a.inst); tiles are numbered instance-major.
+//
 // Persistent: workgroup w owns the contiguous tile range
 // [w C, (w+1) C), C = ceil(tiles / gridDim.x), tile t = (t % tiles_x,
 // t / tiles_x).  Twiddles, the z kinetic table and (x passes) the guide
 // tables live in LDS, so while a tile is transformed the only vector-memory
 // reads in flight are the prefetch of the next tile's values (and of its
 // per-pencil kinetic factors), which therefore overlap the arithmetic.
-template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN>
+template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH>
 __global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM))
 pass_kernel(PassArgs a) {
   using G = PassGeom<S, N, PX, PO, CONTIG, EM>;
@@ -673,7 +698,7 @@ pass_kernel(PassArgs a) {
   // tiles of one field; a batched launch covers ninst fields of this grid,
   // instance-major (global tile tg = instance * tpi + local tile)
   const int tpi = a.tiles_x * a.tiles_y;
-  const int ntiles = tpi * (a.ninst > 0 ? a.ninst : 1);
+  const int ntiles = tpi * (BATCH ? a.ninst : 1);
   const int chunk = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
   const int tbeg = (int)blockIdx.x * chunk;
   const int tend = min(ntiles, tbeg + chunk);
@@ -681,11 +706,13 @@ pass_kernel(PassArgs a) {
 
   const bool ctap = CONTIG && a.vkind == V_CTAP;
   const long long gplane = (long long)MAX_GUIDES * a.nz * a.nx;    // one guide table (A or D)
-  auto field_in = [&](int k) -> const S* { return a.ninst > 0 ? (const S*)a.inst[k].in : (const S*)a.in; };
-  auto field_out = [&](int k) -> S* { return a.ninst > 0 ? (S*)a.inst[k].out : (S*)a.out; };
-  auto guideA = [&](int k) -> const double* { return a.ninst > 0 ? a.inst[k].ctap : a.ctapA; };
-  auto guideB = [&](int k) -> const double* { return a.ninst > 0 ? a.inst[k].ctap + 2 * gplane : a.ctapB; };
-
+  // Batch descriptors are read with scalar loads (uniform index, constant
+  // address space) and only when the instance changes, so the field pointers
+  // stay in scalar registers and no vector-memory wait is tied to them.
+  const InstDesc SSF_CONST* idesc = (const InstDesc SSF_CONST*)a.inst;
+  const S* in_k = (const S*)a.in;                                  // field read by load_tile
+  S* out_k = (S*)a.out;                                            // field written by the tile loop
+  int k_in = -1, k_out = -1;
   // tables into LDS (once per workgroup; the guide B table again when the instance changes)
   for (int j = threadIdx.x; j < N; j += WG) {
     s_tw[j] = a.tw[j];
@@ -702,9 +729,13 @@ pass_kernel(PassArgs a) {
   S raw[E];
   double2 kx_n, ky_n;
   auto load_tile = [&](int tg) {
-    const int k = a.ninst > 0 ? tg / tpi : 0;
+    const int k = BATCH ? __builtin_amdgcn_readfirstlane(tg / tpi) : 0;
     const int t = tg - k * tpi;
-    const S* __restrict__ in = field_in(k);
+    if (BATCH && k != k_in) {
+      in_k = (const S*)idesc[k].in;
+      k_in = k;
+    }
+    const S* __restrict__ in = in_k;
     Pen<G, r0> p;
     pencils(p, a, t);
 #pragma unroll
@@ -714,7 +745,7 @@ pass_kernel(PassArgs a) {
         S v;
         v.x = 0;
         v.y = 0;
-        if (p.ok[u]) v = in[elem_off<G>(p.off[u], p.i[u] + m * (N / r0), a)];
+        if (p.ok[u]) v = ldraw(in + elem_off<G>(p.off[u], p.i[u] + m * (N / r0), a));
         raw[u * r0 + m] = v;
       }
     if constexpr (KZ) {
@@ -731,21 +762,25 @@ pass_kernel(PassArgs a) {
   int plane = -1, binst = -1;
   if (prefetch) load_tile(tbeg);
   for (int tg = tbeg; tg < tend; ++tg) {
-    const int k = a.ninst > 0 ? tg / tpi : 0;
+    const int k = BATCH ? __builtin_amdgcn_readfirstlane(tg / tpi) : 0;
     const int t = tg - k * tpi;
     const int t1 = t / a.tiles_x;
-    S* __restrict__ out = field_out(k);
+    if (BATCH && k != k_out) {
+      out_k = (S*)idesc[k].out;
+      k_out = k;
+    }
+    S* __restrict__ out = out_k;
     if constexpr (CONTIG) {
       if (ctap && (k != binst || t1 != plane)) {
         // guide tables of this plane (A_g(x, z)) and instance (B_g(y)) into LDS
         __syncthreads();
         const long long pl = (long long)a.nz * a.nx;
-        const double* A = guideA(k);
+        const double* A = BATCH ? idesc[k].ctap : a.ctapA;
         for (int j = threadIdx.x; j < MAX_GUIDES * N; j += WG)
-          s_A[j] = A[(j / N) * pl + (long long)t1 * a.nx + (j % N)];
+          s_A[j] = ldg(A + (j / N) * pl + (long long)t1 * a.nx + (j % N));
         if (k != binst) {
-          const double* B = guideB(k);
-          for (int j = threadIdx.x; j < MAX_GUIDES * a.ny; j += WG) s_dyn[j] = B[j];
+          const double* B = BATCH ? idesc[k].ctap + 2 * gplane : a.ctapB;
+          for (int j = threadIdx.x; j < MAX_GUIDES * a.ny; j += WG) s_dyn[j] = ldg(B + j);
         }
         __syncthreads();
         plane = t1;
@@ -942,10 +977,8 @@ hipError_t launch_persistent(K kernel, int wg, size_t dyn, PassArgs a, dim3 tile
   return hipGetLastError();
 }
 
-// The lean x kernel serves the fused x pass of the steady-state steps (only
-// the potential phase, guide potential or none); lean y/z kernels serve
-// every strided pass without a reduction.
-template <typename S, int N, int DT, int VAR>
+// y/z passes of one tile variant (B: batched launch).
+template <typename S, int N, int DT, int VAR, bool B>
 hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t st) {
   constexpr int SX = Shape<N>::sx(DT, VAR), SO = Shape<N>::so(DT, VAR), SM = Shape<N>::sm(DT, VAR);
   constexpr int WGS = PassGeom<S, N, SX, SO, false, SM>::WG;
@@ -953,12 +986,16 @@ hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t s
   switch (kind) {
     case STRIDED_FWD:
       if (a.post == 0)
-        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true>, WGS, 0, a, tiles, st, occ[0]);
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false>, WGS, 0, a, tiles, st, occ[1]);
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true, B>, WGS, 0, a, tiles, st,
+                                 occ[0]);
+      if constexpr (B) return hipErrorInvalidValue;
+      else
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false, false>, WGS, 0, a, tiles,
+                                 st, occ[1]);
     case STRIDED_INV:
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true>, WGS, 0, a, tiles, st, occ[2]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true, B>, WGS, 0, a, tiles, st, occ[2]);
     case STRIDED_FUSED:
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true>, WGS, 0, a, tiles, st, occ[3]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true, B>, WGS, 0, a, tiles, st, occ[3]);
     default:
       return hipErrorInvalidValue;
   }
@@ -966,8 +1003,10 @@ hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t s
 
 // The lean x kernel serves the fused x pass of the steady-state steps (only
 // the potential phase, guide potential or none, real time); lean y/z kernels
-// serve every strided pass without a reduction.
-template <typename S, int N, int DT>
+// serve every strided pass without a reduction.  Batched launches (B) exist
+// for the passes of a real-time step: x forward with a pre phase, x inverse
+// with a post phase, the lean fused x pass and the lean y/z passes.
+template <typename S, int N, int DT, bool B>
 hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hipStream_t st) {
   constexpr int CR = Shape<N>::cr();
   constexpr int WGC = PassGeom<S, N, CR, 1, true, 1>::WG;
@@ -976,23 +1015,32 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
   const bool lean_x = a.pre == 0 && a.post == 0 && !a.imag && (a.vkind == V_CTAP || a.vkind == V_NONE);
   switch (kind) {
     case CONTIG_FWD:
-      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, false, 1, false>, WGC, dync, a, tiles, st, occ[0]);
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, false, 1, false, B>, WGC, dync, a, tiles, st,
+                               occ[0]);
     case CONTIG_INV:
-      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, true, 1, false>, WGC, dync, a, tiles, st, occ[1]);
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, true, 1, false, B>, WGC, dync, a, tiles, st,
+                               occ[1]);
     case CONTIG_FUSED:
       if (lean_x)
-        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true>, WGC, dync, a, tiles, st, occ[2]);
-      return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false>, WGC, dync, a, tiles, st, occ[3]);
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B>, WGC, dync, a, tiles, st,
+                                 occ[2]);
+      if constexpr (B) return hipErrorInvalidValue;
+      else
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false, false>, WGC, dync, a, tiles, st,
+                                 occ[3]);
     default:
-      return variant == 1 ? launch_strided<S, N, DT, 1>(kind, a, tiles, st)
-                          : launch_strided<S, N, DT, 0>(kind, a, tiles, st);
+      return variant == 1 ? launch_strided<S, N, DT, 1, B>(kind, a, tiles, st)
+                          : launch_strided<S, N, DT, 0, B>(kind, a, tiles, st);
   }
 }
 
 template <int N>
 hipError_t launch_any(int kind, int dt_index, int variant, const PassArgs& a, dim3 grid, hipStream_t st) {
-  return dt_index == 0 ? launch_pass<float2, N, 0>(kind, variant, a, grid, st)
-                       : launch_pass<double2, N, 1>(kind, variant, a, grid, st);
+  if (a.ninst > 0)
+    return dt_index == 0 ? launch_pass<float2, N, 0, true>(kind, variant, a, grid, st)
+                         : launch_pass<double2, N, 1, true>(kind, variant, a, grid, st);
+  return dt_index == 0 ? launch_pass<float2, N, 0, false>(kind, variant, a, grid, st)
+                       : launch_pass<double2, N, 1, false>(kind, variant, a, grid, st);
 }
 
 template <int N, int DT, int VAR>
