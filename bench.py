@@ -1,30 +1,48 @@
 #!/usr/bin/env python
-"""Benchmark: split-step Fourier propagation of the three-guide workload.
+"""Benchmark of the split-step Fourier path on one GPU.  Prints one JSON line.
 
-Workload (default): 256 x 256 x 512 grid on [-8,8)^2 x [-64,64), three
-Gaussian guides (v0 = 40, sigma = 0.6, d0 = 3, delta = 1.2), initial state =
-transverse ground state of guide 1 (2000 imaginary-time steps at dtau = 0.002
-on the 256 x 256 plane) x a z Gaussian of width 4 at z0 = -30 moving with
-k_z = 3; real-time Strang steps at dt = 0.002 with an observation (norm,
-moments, guide populations) every 100 steps.  Storage complex64 with FP64
-arithmetic (the fast mode); the complex128 mode is timed on the same input
-for the c64-vs-c128 comparison and the accuracy of c64 is stated against it.
+Headline workload (the `value`): the three-guide transfer on a
+256 x 256 x 512 grid on [-8,8)^2 x [-64,64), guides v0 = 40, sigma = 0.6,
+d0 = 3, delta = 1.2; initial state = transverse ground state of guide 1
+(2000 imaginary-time steps at dtau = 0.002 on the 256 x 256 plane) times a
+z Gaussian of width 4 at z0 = -30 moving with k_z = 3; real-time Strang steps
+at dt = 0.002 with an observation (norm, moments, guide populations) every 100
+steps.  Storage complex64 with FP64 arithmetic.  The timed region covers
+exactly --steps steps of the measured field, started from the initial state
+(the warm-up steps run on a scratch copy), bracketed by device
+synchronisation; the field is resident in HBM before it starts.  The same
+steps in complex128 storage give the accuracy of complex64 (relative L2,
+final target-guide population, norm drift) and the c64/c128 speedup.
 
-One "step" = one Strang step of the whole hot path.  The timed region covers
-exactly --steps steps, bracketed by device synchronisation; the field is
-resident in HBM before it starts.  Per-pass kernel times come from HIP
-events that the library records around each pass launch on its own stream
-during the timed region (ssf_set_timing); the dominant pass gives the
-roofline entry.  The CPU baseline is the FP64 oracle on a bounded sample of
-the same workload (a few full-grid steps).
+Per-pass kernel times come from HIP events that the library records around
+each pass launch on its own stream during the timed region; the dominant
+pass gives the roofline entry.  HBM traffic of that kernel comes from the
+profiler byte counters kept under profiles/ (used only if they were taken
+on the current kernel sources).  The CPU baseline is the FP64 oracle on a
+bounded sample of the same workload.
 
-Prints one JSON line.
+Further sections (each can be skipped with --sections):
+  batch    96 instances of uneven grids (seeded), complex64, 2000 steps at
+           dt = 0.004 in one batch (grouped persistent launches, graph
+           replay, tuned tiles): aggregate updates/s, final target-guide
+           population distribution, speed and accuracy against the plain
+           complex128 path.
+  adjoint  128 x 128 x 256 gradient of the final target population with
+           respect to 2 x 16 B-spline coefficients of the outer guide
+           centres, 4000 steps at dt = 0.004, checkpoints every 64 steps:
+           time and device memory per gradient, complex64 vs complex128,
+           against the cost of central differences with the plain path.
+  c3       512^3, seeded +-5 % guide parameters, 500 imaginary-time steps on
+           the full grid, then 5000 real-time steps in complex64 and
+           complex128.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,105 +51,391 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point split-step updates/s + HBM GB/s vs roofline, c64 vs c128 at ≤1e-4 L2"
+ALL_SECTIONS = ("c128", "cpu", "batch", "adjoint", "c3")
 
 
-def initial_state(torch, ssf, cfg, dtype, device):
-    """phi_1(x, y) (imaginary-time ground state of guide 1 alone at z0) times a
-    moving z Gaussian, normalised on the grid."""
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# initial states (all arithmetic in the library; torch builds the product form)
+# ---------------------------------------------------------------------------
+def transverse_ground_state(torch, ssf, g, v0, sigma, xc, steps, dtau, device):
+    """(1, Ny, Nx) complex128: imaginary-time ground state of one guide
+    (depth v0, width sigma, centre x = xc) on the transverse plane of g."""
     import numpy as np
-    g = cfg["grid"]
-    gd = cfg["guides"]
-    z0 = cfg["z0"]
-    iz0 = int(round((z0 - g.lo[2]) / g.spacing(2)))
     s2 = ssf.Solver((g.n[0], g.n[1], 1), (g.lo[0], g.lo[1], 0.0), (g.hi[0], g.hi[1], 1.0), "c128", device=device)
-    s2.set_guides(gd.v0[:1], gd.sigma[:1], gd.xc[0:1, iz0:iz0 + 1])
+    s2.set_guides([v0], [sigma], np.array([[xc]], dtype=np.float64))
     x = torch.tensor(g.axis(0), dtype=torch.float64, device=device)
     y = torch.tensor(g.axis(1), dtype=torch.float64, device=device)
-    xc = float(gd.xc[0, iz0])
-    phi = torch.exp(-((x[None, :] - xc) ** 2 + y[:, None] ** 2) / (2 * 0.36)).to(torch.complex128)
+    phi = torch.exp(-((x[None, :] - xc) ** 2 + y[:, None] ** 2) / (2 * sigma ** 2)).to(torch.complex128)
     phi = phi.reshape(1, g.n[1], g.n[0]).contiguous()
-    s2.step(phi, cfg["imag_steps"], cfg["dt"], imag=True)
+    s2.step(phi, steps, dtau, imag=True)
+    s2.close()
+    return phi
+
+
+def packet(torch, g, phi, z0, zwidth, kz, device):
+    """phi(x, y) * exp(-(z - z0)^2 / (2 w^2) + i kz z), normalised on the grid (complex128)."""
     z = torch.tensor(g.axis(2), dtype=torch.float64, device=device)
-    fz = torch.exp(-((z - z0) ** 2) / (2 * cfg["zwidth"] ** 2)).to(torch.complex128) * torch.exp(1j * cfg["kz"] * z)
+    fz = torch.exp(-((z - z0) ** 2) / (2 * zwidth ** 2)).to(torch.complex128) * torch.exp(1j * kz * z)
     psi = (fz[:, None, None] * phi).contiguous()
     nrm = torch.sqrt(torch.sum(torch.abs(psi) ** 2) * g.dv)
-    psi = (psi / nrm).to(dtype).contiguous()
-    s2.close()
-    return psi
+    return (psi / nrm).contiguous()
 
 
-def run_mode(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device):
-    g = cfg["grid"]
-    gd = cfg["guides"]
+def guide_index(g, z0):
+    return int(round((z0 - g.lo[2]) / g.spacing(2)))
+
+
+def c2_initial_state(torch, ssf, cfg, device):
+    g, gd = cfg["grid"], cfg["guides"]
+    xc = float(gd.xc[0, guide_index(g, cfg["z0"])])
+    phi = transverse_ground_state(torch, ssf, g, gd.v0[0], gd.sigma[0], xc, cfg["imag_steps"], cfg["dt"], device)
+    return packet(torch, g, phi, cfg["z0"], cfg["zwidth"], cfg["kz"], device)
+
+
+# ---------------------------------------------------------------------------
+# one timed run of a single field
+# ---------------------------------------------------------------------------
+def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tune=True, timing=True):
+    g, gd = cfg["grid"], cfg["guides"]
     s = ssf.Solver(g.n, g.lo, g.hi, dtype, device=device)
     s.set_guides(gd.v0, gd.sigma, gd.xc)
     s.set_partition(gd.x_lo, gd.x_hi)
-    tiles, tune_us = s.tune(reps=10)          # tile autotuner (outside the timed region)
-    s.tune_result = {"choice": tiles, "us": {"axis%d_variant%d" % k: v for k, v in tune_us.items()}}
-    psi = psi0.to(s.tdtype).contiguous().clone()
-    obs = s.obs_buffer(max(1, (steps + warmup) // obs_every))
+    tune_info = None
+    if tune:
+        tiles, tune_us = s.tune(reps=10)          # tile autotuner (outside the timed region)
+        tune_info = {"choice": tiles, "us": {"axis%d_variant%d" % k: v for k, v in tune_us.items()}}
+    obs = s.obs_buffer(max(1, max(steps, warmup) // obs_every))
     if warmup:
-        s.step(psi, warmup, cfg["dt"], obs_every=obs_every, obs_buf=obs)
+        scratch = psi0.to(s.tdtype).contiguous().clone()
+        s.step(scratch, warmup, cfg["dt"], obs_every=obs_every, obs_buf=obs)
+        del scratch
+    psi = psi0.to(s.tdtype).contiguous().clone()
     torch.cuda.synchronize()
-    s.set_timing(True)
+    if timing:
+        s.set_timing(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     ev0.record()
     s.step(psi, steps, cfg["dt"], obs_every=obs_every, obs_buf=obs)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    passes = s.timing_read()
-    s.set_timing(False)
+    passes = s.timing_read() if timing else {}
+    if timing:
+        s.set_timing(False)
     nobs = steps // obs_every
     rec = s.read_obs(obs, nobs) if nobs else None
-    return s, psi, ms, passes, rec
+    s.close()
+    return dict(psi=psi, ms=ms, passes=passes, rec=rec, tune=tune_info)
 
 
-def cpu_baseline(cfg, sample_steps):
-    """FP64 oracle on the host: `sample_steps` full-grid steps of the same workload."""
-    import numpy as np
+def pass_summary(passes):
+    return {k: {"total_ms": v[0], "launches": v[1], "avg_us": 1e3 * v[0] / v[1] if v[1] else None}
+            for k, v in passes.items()}
+
+
+def rel_l2(torch, a, b):
+    d = a.to(torch.complex128) - b.to(torch.complex128)
+    return float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(b.to(torch.complex128)))
+
+
+# ---------------------------------------------------------------------------
+# HBM traffic from the committed profiler counters
+# ---------------------------------------------------------------------------
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ssf_pass.hpp", "ssf_internal.hpp", "ssf_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1309_2451_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_kind, grid_n, dtype):
+    """Bytes per launch (read + write) of one pass kind from the byte-counter
+    summary under profiles/, or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ctap%dx%dx%d_%s.md" % (grid_n[0], grid_n[1], grid_n[2], dtype))
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel sources sha256\[:16\]: `([0-9a-f]+)`", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"^\| %s \| ([0-9.e+]+) \| ([0-9.e+]+) \| ([0-9.e+]+) \|" % re.escape(kernel_kind), txt, re.M)
+    if not m:
+        return None
+    return float(m.group(3))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample
+# ---------------------------------------------------------------------------
+def cpu_baseline(cfg, target_s=15.0):
+    """FP64 oracle on the host: whole-grid steps of the same workload, as many
+    as fit about target_s seconds (at least 2)."""
     import oracle
     import synth
-    g = cfg["grid"]
-    gd = cfg["guides"]
-    rng = np.random.default_rng(0)
+    g, gd = cfg["grid"], cfg["guides"]
     psi = synth.gaussian_packet(g, centre=(gd.xc[0, 0], 0.0, cfg["z0"]), width=(0.3, 0.3, cfg["zwidth"]),
                                 k=(0.0, 0.0, cfg["kz"]))
     V = oracle.ctap_potential(g.shape, g.lo, g.hi, gd.v0, gd.sigma, gd.xc)
-    oracle.step(psi, V, g.lo, g.hi, cfg["dt"], 1)          # warm-up (page-in, thread pool)
     t0 = time.perf_counter()
-    oracle.step(psi, V, g.lo, g.hi, cfg["dt"], sample_steps)
+    psi, _ = oracle.step(psi, V, g.lo, g.hi, cfg["dt"], 1)          # warm-up; sizes the sample
+    one = time.perf_counter() - t0
+    n = max(2, int(target_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.step(psi, V, g.lo, g.hi, cfg["dt"], n)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
-    del rng
-    return {"value": g.points * sample_steps / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d Strang steps of the full %dx%dx%d grid (FP64, OpenMP over pencils), %.1f s"
-                      % (sample_steps, g.n[0], g.n[1], g.n[2], dt)}
+    return {"value": g.points * n / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d Strang steps of the full %dx%dx%d grid with the guide potential (FP64, OpenMP over "
+                      "pencils), %.1f s" % (n, g.n[0], g.n[1], g.n[2], dt)}
+
+
+# ---------------------------------------------------------------------------
+# batched sweep
+# ---------------------------------------------------------------------------
+def section_batch(torch, ssf, device, steps=None, count=96, chunk=50, imag_steps=1000, plain_steps=200):
+    import numpy as np
+    import synth
+    cfg = synth.config4(count)
+    inst = cfg["instances"]
+    dt = cfg["dt"]
+    steps = cfg["steps"] if steps is None else steps
+    log("batch: %d instances, transverse ground states" % len(inst))
+    psi0 = []
+    for it in inst:
+        g, gd = it["grid"], it["guides"]
+        xc = float(gd.xc[0, guide_index(g, it["z0"])])
+        phi = transverse_ground_state(torch, ssf, g, gd.v0[0], gd.sigma[0], xc, imag_steps, 2 * dt, device)
+        psi0.append(packet(torch, g, phi, it["z0"], it["zwidth"], it["kz"], device))
+    b = ssf.Batch([(it["grid"].n, it["grid"].lo, it["grid"].hi) for it in inst],
+                  [(it["guides"].v0, it["guides"].sigma, it["guides"].xc) for it in inst],
+                  [it["guides"].x_lo for it in inst], [it["guides"].x_hi for it in inst], dtype="c64")
+    t0 = time.perf_counter()
+    b.tune(reps=5)
+    tune_s = time.perf_counter() - t0
+    ngroups, gof = b.groups()
+    points = sum(it["grid"].points for it in inst)
+    # warm-up on scratch fields (also builds the graph for this dt and chunk)
+    fields = [p.to(torch.complex64).contiguous() for p in psi0]
+    b.run(fields, 2 * chunk, dt, chunk=chunk)
+    fields = [p.to(torch.complex64).contiguous() for p in psi0]
+    obs = b.obs_buffer()
+    torch.cuda.synchronize()
+    log("batch: timed run, %d steps" % steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    b.run(fields, steps, dt, chunk=chunk, obs_buf=obs)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    rec = b.read_obs(obs)
+    p3 = np.array([r["pop"][2] for r in rec])
+    norms = np.array([r["norm"] for r in rec])
+    ups = points * steps / (ms * 1e-3)
+    # plain complex128 path, one handle per instance, untuned
+    log("batch: plain complex128 rate, %d steps per instance" % plain_steps)
+    t128 = 0.0
+    for it, p in zip(inst, psi0):
+        g, gd = it["grid"], it["guides"]
+        s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
+        s.set_guides(gd.v0, gd.sigma, gd.xc)
+        s.set_partition(gd.x_lo, gd.x_hi)
+        f = p.clone()
+        s.step(f, 2, dt)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(f, plain_steps, dt)
+        e1.record()
+        torch.cuda.synchronize()
+        t128 += e0.elapsed_time(e1)
+        s.close()
+    ups128 = points * plain_steps / (t128 * 1e-3)
+    # accuracy: the first instance of each grid size, full run in complex128
+    acc = []
+    seen = set()
+    for i, it in enumerate(inst):
+        if it["grid"].n in seen:
+            continue
+        seen.add(it["grid"].n)
+        g, gd = it["grid"], it["guides"]
+        s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
+        s.set_guides(gd.v0, gd.sigma, gd.xc)
+        s.set_partition(gd.x_lo, gd.x_hi)
+        f = psi0[i].clone()
+        s.step(f, steps, dt)
+        o = s.observables(f)
+        acc.append({"instance": i, "grid": list(g.n), "rel_l2_c64_vs_c128": rel_l2(torch, fields[i], f),
+                    "p3_c64": float(p3[i]), "p3_c128": float(o["pop"][2]),
+                    "p3_abs_err": abs(float(p3[i]) - float(o["pop"][2]))})
+        s.close()
+    b.close()
+    hist, edges = np.histogram(p3, bins=10, range=(0.0, 1.0))
+    sizes = {}
+    for it in inst:
+        k = "x".join(str(v) for v in it["grid"].n)
+        sizes[k] = sizes.get(k, 0) + 1
+    return {
+        "workload": "%d instances, grids %s, guides v0=40 sigma=0.6, d0~U[2.5,3.5], delta~U[0.8,1.6], "
+                    "k_z~U[2,4] (seed 4), complex64, dt=%g, %d steps, chunk %d steps per graph replay"
+                    % (len(inst), sizes, dt, steps, chunk),
+        "points_total": points, "groups": ngroups, "value": ups, "unit": "updates/s",
+        "ms": ms, "tune_s": tune_s,
+        "plain_c128_value": ups128, "plain_c128_steps": plain_steps,
+        "speedup_vs_plain_c128": ups / ups128,
+        "p3_quantiles": {q: float(np.quantile(p3, q)) for q in (0.0, 0.1, 0.25, 0.5, 0.75, 0.9, 1.0)},
+        "p3_mean": float(p3.mean()), "p3_histogram": {"edges": [float(e) for e in edges], "counts": hist.tolist()},
+        "max_norm_drift": float(np.max(np.abs(norms - 1.0))),
+        "accuracy_vs_c128": acc,
+    }
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient
+# ---------------------------------------------------------------------------
+def section_adjoint(torch, ssf, device, steps=None):
+    import numpy as np
+    import synth
+    from paper_1309_2451_amd.fidelity import FidelityFn, FidelityProblem
+    cfg = synth.config5()
+    g = cfg["grid"]
+    steps = cfg["steps"] if steps is None else steps
+    a, b = cfg["zrange"]
+    # initial state from the nominal (unperturbed) profile, held fixed
+    nominal = synth.ctap_profile(g.axis(2), 3.0, 1.2, 6.0, -6.0, 8.0)
+    xc1 = float(nominal[0, guide_index(g, cfg["z0"])])
+    phi = transverse_ground_state(torch, ssf, g, cfg["v0"][0], cfg["sigma"][0], xc1, 1000, 2 * cfg["dt"], device)
+    psi0 = packet(torch, g, phi, cfg["z0"], cfg["zwidth"], cfg["kz"], device)
+    out = {"workload": "gradient of the final target-guide population w.r.t. 2 x %d B-spline coefficients, "
+                       "%dx%dx%d, dt=%g, %d steps, checkpoints every %d steps"
+                       % (cfg["M"], g.n[0], g.n[1], g.n[2], cfg["dt"], steps, cfg["ckpt_every"])}
+    grads = {}
+    for dtype in ("c64", "c128"):
+        log("adjoint: %s gradient" % dtype)
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        s = ssf.Solver(g.n, g.lo, g.hi, dtype, device=device)
+        s.tune(reps=5)
+        p0 = psi0.to(s.tdtype).contiguous()
+        prob = FidelityProblem(s, p0, cfg["v0"], cfg["sigma"], np.zeros(g.n[2]), cfg["M"], (a, b),
+                               cfg["x_lo"], cfg["x_hi"], cfg["dt"], steps, cfg["ckpt_every"])
+        c = torch.tensor(cfg["coeffs"], dtype=torch.float64, requires_grad=True)
+        F = FidelityFn.apply(c, prob)                  # warm-up (tables, kernels)
+        F.backward()
+        c.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = FidelityFn.apply(c, prob)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        free1, _ = torch.cuda.mem_get_info()
+        grads[dtype] = c.grad.numpy().copy()
+        out[dtype] = {"F": float(F.detach()), "forward_s": t1 - t0, "backward_s": t2 - t1, "gradient_s": t2 - t0,
+                      "device_bytes": int(free0 - free1)}
+        del prob, p0
+        s.close()
+        torch.cuda.empty_cache()
+    # plain complex128 forward (no checkpoints, no tuning): the unit of a finite-difference gradient
+    B = ssf.bspline_basis(cfg["M"], a, b, g.axis(2))
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
+    s.set_guides(cfg["v0"], cfg["sigma"], np.stack([B @ cfg["coeffs"][0], np.zeros(g.n[2]), B @ cfg["coeffs"][1]]))
+    f = psi0.clone()
+    s.step(f, 4, cfg["dt"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(f, steps, cfg["dt"])
+    torch.cuda.synchronize()
+    fwd128 = time.perf_counter() - t0
+    s.close()
+    nparam = 2 * cfg["M"]
+    g64, g128 = grads["c64"], grads["c128"]
+    out["plain_c128_forward_s"] = fwd128
+    out["central_fd_c128_s"] = 2 * nparam * fwd128
+    out["speedup_c64_adjoint_vs_fd_c128"] = 2 * nparam * fwd128 / out["c64"]["gradient_s"]
+    out["speedup_c64_adjoint_vs_c128_adjoint"] = out["c128"]["gradient_s"] / out["c64"]["gradient_s"]
+    out["grad_rel_err_c64_vs_c128"] = float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128))
+    out["F_abs_err_c64_vs_c128"] = abs(out["c64"]["F"] - out["c128"]["F"])
+    out["grad_norm"] = float(np.linalg.norm(g128))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 512^3
+# ---------------------------------------------------------------------------
+def section_c3(torch, ssf, device, steps=None, obs_every=100):
+    import synth
+    cfg = synth.config3()
+    g, gd = cfg["grid"], cfg["guides"]
+    steps = cfg["steps"] if steps is None else steps
+    log("c3: initial state (%d imaginary-time steps on the full grid)" % cfg["imag_steps"])
+    xc = float(gd.xc[0, guide_index(g, cfg["z0"])])
+    phi = transverse_ground_state(torch, ssf, g, gd.v0[0], gd.sigma[0], xc, 2000, cfg["dt"], device)
+    psi = packet(torch, g, phi, cfg["z0"], cfg["zwidth"], 0.0, device)
+    del phi
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
+    s.set_guides(gd.v0, gd.sigma, gd.xc)
+    s.step(psi, cfg["imag_steps"], cfg["dt"], imag=True)
+    s.close()
+    z = torch.tensor(g.axis(2), dtype=torch.float64, device=device)
+    psi.mul_(torch.exp(1j * cfg["kz"] * z)[:, None, None])
+    out = {"workload": "512^3 guide transfer, v0 and sigma +-5%% (seed 3), %d imaginary + %d real steps, dt=%g"
+                       % (cfg["imag_steps"], steps, cfg["dt"])}
+    runs = {}
+    for dtype in ("c64", "c128"):
+        log("c3: %s, %d steps" % (dtype, steps))
+        r = timed_run(torch, ssf, cfg, psi, dtype, steps, 20, obs_every, device)
+        ups = g.points * steps / (r["ms"] * 1e-3)
+        esize = 8 if dtype == "c64" else 16
+        launches = sum(c for _, c in r["passes"].values())
+        out[dtype] = {"value": ups, "ms_per_step": r["ms"] / steps, "passes": pass_summary(r["passes"]),
+                      "step_algorithmic_gbs": launches * 2.0 * esize * g.points / (r["ms"] * 1e-3) / 1e9,
+                      "final_p3": float(r["rec"][-1]["pop"][2]), "norm_drift": float(r["rec"][-1]["norm"] - 1.0),
+                      "tiles": r["tune"]}
+        runs[dtype] = r["psi"]
+    out["c64_vs_c128_rel_l2"] = rel_l2(torch, runs["c64"], runs["c128"])
+    out["c64_speedup_vs_c128"] = out["c64"]["value"] / out["c128"]["value"]
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--obs-every", type=int, default=100)
-    ap.add_argument("--grid", type=str, default="256,256,512", help="Nx,Ny,Nz of the guide workload")
-    ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison run")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--grid", type=str, default="256,256,512", help="Nx,Ny,Nz of the headline workload")
+    ap.add_argument("--sections", type=str, default=",".join(ALL_SECTIONS),
+                    help="comma list of extra sections to run: " + ",".join(ALL_SECTIONS) + " (none: headline only)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--imag-steps", type=int, default=None,
                     help="imaginary-time steps of the transverse ground state (default: the workload's 2000)")
+    ap.add_argument("--batch-steps", type=int, default=None)
+    ap.add_argument("--adjoint-steps", type=int, default=None)
+    ap.add_argument("--c3-steps", type=int, default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain device copy of one field (for scaling profiler byte counters)")
+                    help="also run the library's plain field copy (2 x field bytes per launch), which "
+                         "calibrates profiler byte counters")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % a.gpus,
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (got --gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    sections = [x for x in a.sections.split(",") if x and x != "none"]
+    for x in sections:
+        if x not in ALL_SECTIONS:
+            ap.error("unknown section %r" % x)
 
-    import numpy as np
     import torch
 
     import synth
@@ -143,22 +447,22 @@ def main():
     if a.imag_steps is not None:
         cfg["imag_steps"] = a.imag_steps
     g = cfg["grid"]
-    print("bench: building initial state on %s" % (g.n,), file=sys.stderr, flush=True)
-    psi0 = initial_state(torch, ssf, cfg, torch.complex128, device)
+    log("initial state on %s" % (g.n,))
+    psi0 = c2_initial_state(torch, ssf, cfg, device)
 
-    print("bench: c64 run, %d warmup + %d timed steps" % (a.warmup, a.steps), file=sys.stderr, flush=True)
-    s64, psi64, ms64, pass64, rec64 = run_mode(torch, ssf, cfg, psi0, "c64", a.steps, a.warmup, a.obs_every, device)
+    log("c64 run, %d warmup + %d timed steps" % (a.warmup, a.steps))
+    r64 = timed_run(torch, ssf, cfg, psi0, "c64", a.steps, a.warmup, a.obs_every, device)
+    ms64 = r64["ms"]
     ups64 = g.points * a.steps / (ms64 * 1e-3)
 
-    # roofline entry: dominant pass kind of the timed region
+    # roofline entry: the pass kind with the largest total time in the timed region
     esize = 8
-    dom = max(pass64.items(), key=lambda kv: kv[1][0])
-    dom_name, (dom_ms, dom_n) = dom
+    dom_name, (dom_ms, dom_n) = max(r64["passes"].items(), key=lambda kv: kv[1][0])
     avg_s = dom_ms * 1e-3 / max(dom_n, 1)
     bytes_per_launch = 2.0 * esize * g.points            # read + write psi once
     achieved = bytes_per_launch / avg_s / 1e9
-    # whole-step algorithmic bandwidth: passes per step x 2 x esize x points
-    launches = sum(c for _, c in pass64.values())
+    traffic = measured_traffic(dom_name, g.n, "c64")
+    launches = sum(c for _, c in r64["passes"].values())
     step_gbs = launches * 2.0 * esize * g.points / (ms64 * 1e-3) / 1e9
 
     out = {
@@ -174,50 +478,66 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "three-guide CTAP %dx%dx%d, complex64 storage, FP64 arithmetic, dt=0.002, "
+        "config": {"workload": "three-guide transfer %dx%dx%d, complex64 storage, FP64 arithmetic, dt=0.002, "
                                "observables every %d steps" % (g.n[0], g.n[1], g.n[2], a.obs_every),
                    "grid": list(g.n), "storage": "complex64", "arithmetic": "f64", "obs_every": a.obs_every},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom_name,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name,
                      "kernel_avg_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch},
         "step_algorithmic_gbs": step_gbs,
+        "step_algorithmic_frac": step_gbs / HBM_PEAK_GBS,
         "passes_per_step": launches / a.steps,
-        "pass_times_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in pass64.items()},
-        "tiles": s64.tune_result,
+        "pass_times": pass_summary(r64["passes"]),
+        "tiles": r64["tune"],
     }
-    if rec64 is not None and len(rec64):
-        out["final_populations"] = [float(v) for v in rec64[-1]["pop"]]
-        out["norm_drift"] = float(rec64[-1]["norm"] - 1.0)
+    if r64["rec"] is not None and len(r64["rec"]):
+        out["final_populations"] = [float(v) for v in r64["rec"][-1]["pop"]]
+        out["norm_drift"] = float(r64["rec"][-1]["norm"] - 1.0)
 
-    if not a.no_c128:
-        print("bench: c128 run", file=sys.stderr, flush=True)
-        s128, psi128, ms128, pass128, rec128 = run_mode(torch, ssf, cfg, psi0, "c128", a.steps, a.warmup,
-                                                        a.obs_every, device)
-        ups128 = g.points * a.steps / (ms128 * 1e-3)
-        d = (psi64.to(torch.complex128) - psi128)
-        relL2 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(psi128))
-        dom128 = max(pass128.items(), key=lambda kv: kv[1][0])
-        avg128 = dom128[1][0] * 1e-3 / max(dom128[1][1], 1)
-        out["c128"] = {"value": ups128, "ms_per_step": ms128 / a.steps,
-                       "kernel": dom128[0], "kernel_avg_us": avg128 * 1e6,
-                       "achieved_gbs": 2.0 * 16 * g.points / avg128 / 1e9}
+    if "c128" in sections:
+        log("c128 run")
+        r128 = timed_run(torch, ssf, cfg, psi0, "c128", a.steps, a.warmup, a.obs_every, device)
+        ups128 = g.points * a.steps / (r128["ms"] * 1e-3)
+        d128, (m128, n128) = max(r128["passes"].items(), key=lambda kv: kv[1][0])
+        avg128 = m128 * 1e-3 / max(n128, 1)
+        out["c128"] = {"value": ups128, "ms_per_step": r128["ms"] / a.steps, "kernel": d128,
+                       "kernel_avg_us": avg128 * 1e6, "achieved_gbs": 2.0 * 16 * g.points / avg128 / 1e9,
+                       "pass_times": pass_summary(r128["passes"]), "tiles": r128["tune"]}
+        if r128["rec"] is not None and len(r128["rec"]):
+            out["c128"]["final_populations"] = [float(v) for v in r128["rec"][-1]["pop"]]
+            out["c128"]["norm_drift"] = float(r128["rec"][-1]["norm"] - 1.0)
+            if "final_populations" in out:
+                out["c64_vs_c128_p3_abs_err"] = abs(out["final_populations"][2] - out["c128"]["final_populations"][2])
         out["c64_speedup_vs_c128"] = ups64 / ups128
-        out["c64_vs_c128_rel_l2"] = relL2
-        out["c64_vs_c128_steps"] = a.steps + a.warmup
-        s128.close()
+        out["c64_vs_c128_rel_l2"] = rel_l2(torch, r64["psi"], r128["psi"])
+        out["c64_vs_c128_steps"] = a.steps
+        del r128
     if a.calibrate_copy:
-        # a plain copy of one complex64 field: 2 * 8 * points bytes of HBM traffic per launch
-        src = psi64.contiguous()
+        log("plain copy of one complex64 field, 3 launches")
+        s = ssf.Solver(g.n, g.lo, g.hi, "c64", device=device)
+        src = r64["psi"]
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            s.copy(src, dst)
         torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = 2 * src.numel() * src.element_size()
-    s64.close()
+        s.close()
+        out["copy_calibration"] = {"bytes_per_launch": 2 * src.numel() * src.element_size(), "launches": 3}
+        del dst
+    del r64
+    torch.cuda.empty_cache()
 
-    if a.cpu_steps > 0:
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_steps)
+    if "batch" in sections:
+        out["batch"] = section_batch(torch, ssf, device, steps=a.batch_steps)
+        torch.cuda.empty_cache()
+    if "adjoint" in sections:
+        out["adjoint"] = section_adjoint(torch, ssf, device, steps=a.adjoint_steps)
+        torch.cuda.empty_cache()
+    if "c3" in sections:
+        out["c3"] = section_c3(torch, ssf, device, steps=a.c3_steps)
+        torch.cuda.empty_cache()
+    if "cpu" in sections:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -167,6 +167,12 @@ ssf_status ssf_observables(ssf_handle* h, const void* psi, ssf_obs* obs_dev);
 ssf_status ssf_obs_read(ssf_handle* h, const ssf_obs* obs_dev, ssf_obs* host, int64_t count);
 /* Wait for the handle's stream; reports pending asynchronous errors. */
 ssf_status ssf_sync(ssf_handle* h);
+/* dst = src for one field of the handle (storage type, layout as above), by a
+ * plain kernel that reads and writes every value once with the same per-lane
+ * access width as the pass kernels: its HBM traffic is exactly 2 x field
+ * bytes, which calibrates profiler byte counters.  src and dst must not
+ * overlap. */
+ssf_status ssf_copy(ssf_handle* h, const void* src, void* dst);
 
 /* Real-time propagation with checkpoints: before the steps s*every
  * (s = 0 .. ceil(nsteps/every)-1) psi is copied to slot s of ckpt_dev

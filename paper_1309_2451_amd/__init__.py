@@ -245,6 +245,11 @@ class Solver:
     def sync(self):
         _ssf.call("ssf_sync", self.h)
 
+    def copy(self, src, dst):
+        """dst = src by a plain copy kernel (2 x field bytes of HBM traffic)."""
+        self._sync_stream()
+        _ssf.call("ssf_copy", self.h, self._field(src, "src"), self._field(dst, "dst"))
+
 
 class Batch:
     """Many independent instances (an ssf_batch): instance i has its own grid

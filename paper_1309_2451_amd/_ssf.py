@@ -33,7 +33,7 @@ EXPORTS = (
     "ssf_set_potential_table", "ssf_set_potential_ctap", "ssf_clear_potential",
     "ssf_set_partition", "ssf_set_fusion", "ssf_set_timing", "ssf_timing_read",
     "ssf_tune", "ssf_set_tiles", "ssf_get_tiles", "ssf_step", "ssf_fft", "ssf_observables",
-    "ssf_obs_read", "ssf_sync", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
+    "ssf_obs_read", "ssf_sync", "ssf_copy", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
     "ssf_batch_info", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
 )
@@ -105,6 +105,7 @@ def load():
         "ssf_observables": ([hp, vp, vp], i32),
         "ssf_obs_read": ([hp, vp, vp, i64], i32),
         "ssf_sync": ([hp], i32),
+        "ssf_copy": ([hp, vp, vp], i32),
         "ssf_step_ckpt": ([hp, vp, i64, dbl, i64, vp], i32),
         "ssf_step_seq": ([hp, vp, i64, dbl, vp], i32),
         "ssf_adjoint_init": ([hp, vp, vp], i32),

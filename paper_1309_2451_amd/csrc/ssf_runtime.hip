@@ -263,6 +263,15 @@ __global__ void __launch_bounds__(256) obs_finalize_batch(const double* partials
   obs[slot[blockIdx.x]] = o;
 }
 
+// Plain field copy, one value per lane per iteration (grid-stride).
+template <typename S>
+__global__ void __launch_bounds__(256) copy_kernel(const S* in, S* out, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    if constexpr (sizeof(S) == 8) ssf::st2(out + i, ssf::ld2(in + i));
+    else ssf::st2(out + i, ssf::ldraw(in + i));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Handle.
 // ---------------------------------------------------------------------------
@@ -884,6 +893,24 @@ ssf_status ssf_obs_read(ssf_handle* h, const ssf_obs* obs_dev, ssf_obs* host, in
 ssf_status ssf_sync(ssf_handle* h) {
   SSF_TRY(check_handle(h));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return SSF_OK;
+}
+
+ssf_status ssf_copy(ssf_handle* h, const void* src, void* dst) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, src, "src"));
+  SSF_TRY(check_field(h, dst, "dst"));
+  const size_t fb = h->esize * h->npts;
+  const char* a = (const char*)src;
+  const char* b = (const char*)dst;
+  if (a < b + fb && b < a + fb) return fail(SSF_E_INVALID, "src and dst overlap");
+  const long long n = h->npts;
+  const unsigned grid = (unsigned)std::min<long long>(ceil_div(n, 256), 1LL << 20);
+  if (h->dtype == SSF_C64)
+    hipLaunchKernelGGL(copy_kernel<float2>, dim3(grid), dim3(256), 0, h->stream, (const float2*)src, (float2*)dst, n);
+  else
+    hipLaunchKernelGGL(copy_kernel<double2>, dim3(grid), dim3(256), 0, h->stream, (const double2*)src, (double2*)dst, n);
+  HIP_TRY(hipGetLastError());
   return SSF_OK;
 }
 

@@ -344,3 +344,18 @@ def test_tile_variants_and_tuner(dtype, shape):
     s.step(t, 20, 0.01)
     assert rel(host(t), ref_step) < tol_step
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_plain_copy_is_bitwise(dtype):
+    say("copy", dtype)
+    g = synth.Grid((24, 20, 40), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    x = to_dev(synth.random_field(g, 3), s)
+    y = s.empty()
+    s.copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    with pytest.raises(ssf.SSFError):
+        s.copy(x, x)
+    s.close()
