@@ -154,9 +154,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_kind, grid_n, dtype):
-    """Bytes per launch (read + write) of one pass kind from the byte-counter
-    summary under profiles/, or None if absent or taken on other sources."""
+def measured_traffic(kernel_kind, variant, grid_n, dtype):
+    """Bytes per launch (read + write) of one pass kind and tile variant from
+    the byte-counter summary under profiles/, or None if absent or taken on
+    other kernel sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_ctap%dx%dx%d_%s.md" % (grid_n[0], grid_n[1], grid_n[2], dtype))
     if not os.path.exists(path):
         return None
@@ -164,10 +165,14 @@ def measured_traffic(kernel_kind, grid_n, dtype):
     m = re.search(r"kernel sources sha256\[:16\]: `([0-9a-f]+)`", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(r"^\| %s \| ([0-9.e+]+) \| ([0-9.e+]+) \| ([0-9.e+]+) \|" % re.escape(kernel_kind), txt, re.M)
+    m = re.search(r"^\| %s \| %d \| ([0-9.e+]+) \| ([0-9.e+]+) \| ([0-9.e+]+) \|" % (re.escape(kernel_kind), variant),
+                  txt, re.M)
     if not m:
         return None
     return float(m.group(3))
+
+
+PASS_AXIS = {"x_fwd": 0, "x_inv": 0, "x_inv_phase_fwd": 0, "yz_fwd": 1, "yz_inv": 1, "z_fwd_kin_inv": 2}
 
 
 # ---------------------------------------------------------------------------
@@ -461,7 +466,8 @@ def main():
     avg_s = dom_ms * 1e-3 / max(dom_n, 1)
     bytes_per_launch = 2.0 * esize * g.points            # read + write psi once
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = measured_traffic(dom_name, g.n, "c64")
+    dom_var = r64["tune"]["choice"][PASS_AXIS[dom_name]] if r64["tune"] else 0
+    traffic = measured_traffic(dom_name, dom_var, g.n, "c64")
     launches = sum(c for _, c in r64["passes"].values())
     step_gbs = launches * 2.0 * esize * g.points / (ms64 * 1e-3) / 1e9
 
@@ -482,7 +488,7 @@ def main():
                                "observables every %d steps" % (g.n[0], g.n[1], g.n[2], a.obs_every),
                    "grid": list(g.n), "storage": "complex64", "arithmetic": "f64", "obs_every": a.obs_every},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name, "tile_variant": dom_var,
                      "kernel_avg_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch},
         "step_algorithmic_gbs": step_gbs,
         "step_algorithmic_frac": step_gbs / HBM_PEAK_GBS,
