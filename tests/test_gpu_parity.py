@@ -359,3 +359,51 @@ def test_plain_copy_is_bitwise(dtype):
     with pytest.raises(ssf.SSFError):
         s.copy(x, x)
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gradient_workload_copy_vs_oracle_adjoint(dtype):
+    """The gradient workload on a 48 x 48 x 96 copy of its box (16 B-spline
+    coefficients per moving guide, seeded), 200 steps with checkpoints every
+    64: F and dF/dc through the autograd function against the oracle's
+    stored-state adjoint, and central differences (h = 1e-3) in complex128."""
+    say("gradient workload copy", dtype)
+    from paper_1309_2451_amd.fidelity import FidelityFn, FidelityProblem
+    cfg = synth.config5(n=(48, 48, 96))
+    g = cfg["grid"]
+    a, b = cfg["zrange"]
+    M, dt, n = cfg["M"], cfg["dt"], 200
+    nominal = synth.ctap_profile(g.axis(2), 3.0, 1.2, 6.0, -6.0, 8.0)
+    z0 = -8.0
+    iz = int(round((z0 - g.lo[2]) / g.spacing(2)))
+    psi0 = synth.gaussian_packet(g, centre=(nominal[0, iz], 0.0, z0), width=(0.5, 0.5, 3.0), k=(0.0, 0.0, 3.0))
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    prob = FidelityProblem(s, to_dev(psi0, s), cfg["v0"], cfg["sigma"], np.zeros(g.n[2]), M, (a, b),
+                           cfg["x_lo"], cfg["x_hi"], dt, n, cfg["ckpt_every"])
+    c = torch.tensor(cfg["coeffs"], dtype=torch.float64, requires_grad=True)
+    F = FidelityFn.apply(c, prob)
+    F.backward()
+    grad = c.grad.numpy()
+    xc = prob.profile(cfg["coeffs"])
+    F_ref, G_ref, _ = oracle.adjoint_ctap(psi0, g.lo, g.hi, cfg["v0"], cfg["sigma"], xc, dt, n, cfg["x_hi"])
+    Bo = oracle.bspline_basis(M, a, b, g.axis(2))
+    grad_ref = np.stack([G_ref[0] @ Bo, G_ref[2] @ Bo])
+    scale = np.max(np.abs(grad_ref))
+    say("F", float(F.detach()), F_ref, "max|grad|", scale)
+    assert F_ref > 5e-5                       # the packet is in the coupling region
+    if dtype == "c128":
+        assert abs(float(F.detach()) - F_ref) < 1e-12
+        assert np.max(np.abs(grad - grad_ref)) < 1e-9 * scale
+        for k, m in [(0, 5), (1, 8)]:
+            h = 1e-3
+            cp, cm = cfg["coeffs"].copy(), cfg["coeffs"].copy()
+            cp[k, m] += h
+            cm[k, m] -= h
+            fd = (prob.forward(cp) - prob.forward(cm)) / (2 * h)
+            assert abs(fd - grad[k, m]) < 1e-4 * scale, (k, m, fd, grad[k, m])
+    else:
+        assert abs(float(F.detach()) - F_ref) < 1e-6 * max(F_ref, 1e-3)
+        assert np.max(np.abs(grad - grad_ref)) < 1e-3 * scale
+    s.close()
