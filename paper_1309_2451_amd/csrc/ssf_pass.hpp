@@ -309,18 +309,24 @@ __constant__ double SINCOS_C[17] = {
     1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,
     1.0 / 6402373705728000.0, -1.0 / 20922789888000.0, 1.0 / 87178291200.0, -1.0 / 479001600.0,
     1.0 / 3628800.0, -1.0 / 40320.0, 1.0 / 720.0, -1.0 / 24.0, 0.5};
+//
+// LOW (complex64 storage, whose values carry 6e-8 relative rounding): sin to
+// degree 13 and cos to degree 14 after the reduction (truncation error below
+// 3e-14), and degree 11/12 without it (below 7e-12).
+template <bool LOW = false>
 __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   const double q = rint(t * TWO_OVER_PI);
   double r = fma(-q, PIO2_HI, t);
   r = fma(-q, PIO2_LO, r);
   const double r2 = r * r;
-  double ps = SINCOS_C[0];
+  constexpr int S0 = LOW ? 2 : 0, C0 = LOW ? 10 : 8;
+  double ps = SINCOS_C[S0];
 #pragma unroll
-  for (int k = 1; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
+  for (int k = S0 + 1; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
   const double sr = fma(ps * r2, r, r);
-  double pc = SINCOS_C[8];
+  double pc = SINCOS_C[C0];
 #pragma unroll
-  for (int k = 9; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
+  for (int k = C0 + 1; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
   const double cr = fma(-pc, r2, 1.0);
   // quadrant k = q mod 4: odd k swaps sin and cos; sin changes sign for
   // k = 2, 3 and cos for k = 1, 2
@@ -332,29 +338,34 @@ __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   *c = sgn_c * (swap ? sr : cr);
 }
 // exp(-i theta) for |theta| <= pi/4 (no reduction needed): Taylor series of
-// sin to degree 15 and of cos to degree 16, truncation error below 5e-17.
+// sin to degree 15 and of cos to degree 16, truncation error below 5e-17
+// (LOW: degree 11 and 12).
+template <bool LOW = false>
 __device__ __forceinline__ double2 phase_small(double r) {
   const double r2 = r * r;
-  double ps = SINCOS_C[1];
+  constexpr int S0 = LOW ? 3 : 1, C0 = LOW ? 11 : 9;
+  double ps = SINCOS_C[S0];
 #pragma unroll
-  for (int k = 2; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
+  for (int k = S0 + 1; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
   const double sr = fma(ps * r2, r, r);
-  double pc = SINCOS_C[9];
+  double pc = SINCOS_C[C0];
 #pragma unroll
-  for (int k = 10; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
+  for (int k = C0 + 1; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
   const double cr = fma(-pc, r2, 1.0);
   return make_double2(cr, -sr);
 }
 // exp(-i theta)
+template <bool LOW = false>
 __device__ __forceinline__ double2 phase_rt(double theta) {
   double s, c;
-  sincos_fast(theta, &s, &c);
+  sincos_fast<LOW>(theta, &s, &c);
   return make_double2(c, -s);
 }
 // exp(-i theta) in real time, exp(-theta) in imaginary time
+template <bool LOW = false>
 __device__ __forceinline__ double2 phase_factor(double theta, int imag) {
   if (imag) return make_double2(exp(-theta), 0.0);
-  return phase_rt(theta);
+  return phase_rt<LOW>(theta);
 }
 
 // Potential at grid point (x, y, z).  The guide tables always hold MAX_GUIDES
@@ -557,7 +568,11 @@ __device__ __forceinline__ void transform(double2 (&v)[G::E], double2* lds, cons
 // sits at offset off[u] (32-bit: fields have fewer than 2^31 points).
 //   x passes:    row y = c0 of plane z = c1;
 //   y, z passes: column x = c0 of outer pencil c1 (z for y passes, y for z passes).
-// Ragged tiles clamp c0/c1 into range and clear ok.
+// Ragged tiles clamp c0/c1 into range and clear ok: such lanes load, transform
+// and store a copy of the last pencil of the same tile (identical inputs give
+// identical values, so the duplicate stores are harmless), and reductions
+// give them weight zero.  Every lane then issues the same number of memory
+// operations, which lets the compiler wait for the prefetched loads alone.
 template <class G, int r> struct Pen {
   static constexpr int U = G::E / r;
   int i[U], c0[U], c1[U];
@@ -687,6 +702,7 @@ pass_kernel(PassArgs a) {
   constexpr int rl = FUSED ? PL::R[0] : PL::R[PL::S - 1];          // last stage of the last transform
   constexpr bool KZ = !CONTIG && FUSED;                            // z pass with the kinetic factor
   constexpr int UM = E / rm;
+  constexpr bool LOWP = sizeof(S) == 8;                            // complex64 storage: shorter phase series
 
   __shared__ double2 lds[G::LDS];
   __shared__ double2 s_tw[N];
@@ -742,11 +758,7 @@ pass_kernel(PassArgs a) {
     for (int u = 0; u < E / r0; ++u)
 #pragma unroll
       for (int m = 0; m < r0; ++m) {
-        S v;
-        v.x = 0;
-        v.y = 0;
-        if (p.ok[u]) v = ldraw(in + elem_off<G>(p.off[u], p.i[u] + m * (N / r0), a));
-        raw[u * r0 + m] = v;
+        raw[u * r0 + m] = ldraw(in + elem_off<G>(p.off[u], p.i[u] + m * (N / r0), a));
       }
     if constexpr (KZ) {
       static_assert(G::WG % G::P == 0, "one pencil per thread");
@@ -813,7 +825,7 @@ pass_kernel(PassArgs a) {
           double V[E];
           potentials<G, r0>(a, s_A, s_dyn, p, t1, V);
 #pragma unroll
-          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpre, a.imag));
+          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpre, a.imag));
         }
       }
     }
@@ -841,15 +853,15 @@ pass_kernel(PassArgs a) {
             }
             if (a.small_phase) {
 #pragma unroll
-              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_small(V[e] * a.cmid));
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_small<LOWP>(V[e] * a.cmid));
             } else {
 #pragma unroll
-              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt(V[e] * a.cmid));
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt<LOWP>(V[e] * a.cmid));
             }
           } else {
             potentials<G, rm>(a, s_A, s_dyn, p, t1, V);
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cmid, a.imag));
+            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cmid, a.imag));
           }
         }
       } else {
@@ -877,7 +889,7 @@ pass_kernel(PassArgs a) {
         if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, p, t1, V);
         if (a.post & POST_VPHASE) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor(V[e] * a.cpost, a.imag));
+          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpost, a.imag));
         }
         if (a.post & POST_OBS) {
           const double zc = a.lo[2] + t1 * a.d[2];
@@ -929,7 +941,6 @@ pass_kernel(PassArgs a) {
       }
 #pragma unroll
       for (int u = 0; u < E / r; ++u) {
-        if (!p.ok[u]) continue;
 #pragma unroll
         for (int q = 0; q < r; ++q) st2(out + elem_off<G>(p.off[u], p.i[u] + q * (N / r), a), v[u * r + q]);
       }
