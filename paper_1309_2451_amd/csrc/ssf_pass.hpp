@@ -82,7 +82,7 @@ template <class PL, bool REV> struct Order {
 #define SSF_CR_SHIFT 0         // x-pass rows per workgroup scaled by 2^shift
 #endif
 #ifndef SSF_STRIDED_MAXWG
-#define SSF_STRIDED_MAXWG 512  // largest y/z workgroup
+#define SSF_STRIDED_MAXWG 1024 // largest y/z workgroup
 #endif
 
 // Tile shapes.  LDS holds P pencils of N FP64 complex values.
@@ -101,9 +101,13 @@ template <int N> struct Shape {
     while (po > 1 && sx0(dt) * po * N / E > 1024) po /= 2;
     return po;
   }
-  static constexpr int sm0(int dt) {               // variant-0 values-per-thread multiplier
+  // Variant-0 values-per-thread multiplier.  A 1024-thread workgroup leaves
+  // 128 registers per thread: enough for the 8-value plans up to N = 512
+  // (measured faster than 512 threads with 16 values), not for N = 1024.
+  static constexpr int sm0(int dt) {
+    const int maxwg = N >= 1024 && SSF_STRIDED_MAXWG > 512 ? 512 : SSF_STRIDED_MAXWG;
     int em = 1;
-    while (sx0(dt) * so(dt) * N / (E * em) > SSF_STRIDED_MAXWG) em *= 2;
+    while (sx0(dt) * so(dt) * N / (E * em) > maxwg) em *= 2;
     return em;
   }
   // variant 1: half-width tile with the same values per thread, i.e. half
