@@ -120,3 +120,29 @@ def test_batch_tuned_and_zero_steps():
     with pytest.raises(ssf.SSFError):
         b.run(fields, 10, 0.0, chunk=5)
     b.close()
+
+
+def test_batch_single_instance_ragged_grid_and_errors():
+    """One instance on a grid whose lengths need radix-3/5 plans and ragged
+    tiles, c128 against the oracle; invalid descriptions are rejected."""
+    g = synth.Grid((24, 20, 40), (-4.0, -3.0, -8.0), (4.0, 3.0, 8.0))
+    gd = synth.ctap_guides(g, d0=2.0, delta=0.6, v0=12.0, sigma=0.6, z1=2.0, z3=-2.0, wg=3.0)
+    psi = synth.gaussian_packet(g, centre=(-2.0, 0.0, -3.0), width=(0.5, 0.5, 1.5), k=(0.0, 0.0, 2.0))
+    b = ssf.Batch([(g.n, g.lo, g.hi)], [(gd.v0, gd.sigma, gd.xc)], [gd.x_lo], [gd.x_hi], dtype="c128")
+    assert b.groups()[0] == 1
+    f = [torch.from_numpy(psi).to(DEV).contiguous()]
+    obs = b.obs_buffer()
+    b.run(f, 13, 0.01, chunk=5, obs_buf=obs)
+    rec = b.read_obs(obs)
+    V = oracle.ctap_potential(g.shape, g.lo, g.hi, gd.v0, gd.sigma, gd.xc)
+    ref, _ = oracle.step(psi, V, g.lo, g.hi, 0.01, 13)
+    assert np.linalg.norm(f[0].cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-12
+    o = oracle.observables(ref, V, g.lo, g.hi, gd.x_lo, gd.x_hi)
+    assert abs(rec[0]["pop"][2] - o["p3"]) < 1e-12 and abs(rec[0]["norm"] - o["norm"]) < 1e-12
+    b.close()
+    with pytest.raises(ssf.SSFError):
+        ssf.Batch([(g.n, g.lo, g.hi)], [(gd.v0, gd.sigma, gd.xc)], [1.0], [-1.0], dtype="c64")
+    with pytest.raises(ssf.SSFError):
+        ssf.Batch([(g.n, g.lo, g.hi)], [(gd.v0, (0.6, -1.0, 0.6), gd.xc)], [gd.x_lo], [gd.x_hi], dtype="c64")
+    with pytest.raises(ssf.SSFError):
+        ssf.Batch([((24, 20, 7), g.lo, g.hi)], [(gd.v0, gd.sigma, np.zeros((3, 7)))], [0.0], [0.0], dtype="c64")

@@ -407,3 +407,55 @@ def test_gradient_workload_copy_vs_oracle_adjoint(dtype):
         assert abs(float(F.detach()) - F_ref) < 1e-6 * max(F_ref, 1e-3)
         assert np.max(np.abs(grad - grad_ref)) < 1e-3 * scale
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_size_workload_vs_oracle(dtype):
+    """The headline workload at its full size (256 x 256 x 512, three guides) in
+    the configuration the bench times (tuned tiles, fused step chain): three
+    steps against the oracle's three steps, element by element."""
+    say("full-size workload", dtype)
+    cfg = synth.config2()
+    g, gd = cfg["grid"], cfg["guides"]
+    psi0 = synth.gaussian_packet(g, centre=(gd.xc[0, 0], 0.0, cfg["z0"]), width=(0.4, 0.4, cfg["zwidth"]),
+                                 k=(0.0, 0.0, cfg["kz"]))
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_guides(gd.v0, gd.sigma, gd.xc)
+    s.set_partition(gd.x_lo, gd.x_hi)
+    s.tune(reps=3)
+    t = to_dev(psi0, s)
+    n = 3
+    s.step(t, n, cfg["dt"])
+    V = oracle.ctap_potential(g.shape, g.lo, g.hi, gd.v0, gd.sigma, gd.xc)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, cfg["dt"], n)
+    got = host(t)
+    del t
+    tol = 1e-12 if dtype == "c128" else 3 * 6e-8 * np.sqrt(4 * n + 2)
+    err = rel(got, ref)
+    say("rel L2", err)
+    assert err < tol
+    # the largest pointwise deviation relative to the field's peak
+    assert np.max(np.abs(got - ref)) < (1e-12 if dtype == "c128" else 1e-6) * np.max(np.abs(ref))
+    s.close()
+
+
+def test_zero_steps_and_sparse_observations():
+    g = synth.Grid((16, 12, 20), (-3.0, -3.0, -3.0), (3.0, 3.0, 3.0))
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128")
+    V = synth.harmonic_table(g)
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    psi0 = synth.gaussian_packet(g, centre=(0.5, 0.0, 0.0))
+    t = to_dev(psi0, s)
+    assert s.step(t, 0, 0.01) is None
+    assert np.array_equal(host(t), psi0)
+    obs = s.step(t, 7, 0.01, obs_every=10)              # no observation falls due
+    assert obs is None
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, 0.01, 7)
+    assert rel(host(t), ref) < 1e-12
+    with pytest.raises(ssf.SSFError):
+        s.step(t, -1, 0.01)
+    with pytest.raises(ssf.SSFError):
+        s.step(t, 1, float("nan"))
+    s.close()
