@@ -709,7 +709,10 @@ pass_kernel(PassArgs a) {
   constexpr bool LOWP = sizeof(S) == 8;                            // complex64 storage: shorter phase series
 
   __shared__ double2 lds[G::LDS];
-  __shared__ double2 s_tw[N];
+  // Power-of-two plans read twiddle powers W^t only for t < N/2 (the
+  // products of lower powers are formed in registers), so half the table.
+  constexpr int TWN = (!SSF_TW_FULL && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N;
+  __shared__ double2 s_tw[TWN];
   __shared__ double2 s_kz[KZ ? N : 1];
   __shared__ double s_A[CONTIG ? MAX_GUIDES * N : 1];
   __shared__ double red[((WG + 63) / 64) * NRED_OBS];
@@ -735,7 +738,7 @@ pass_kernel(PassArgs a) {
   int k_in = -1, k_out = -1;
   // tables into LDS (once per workgroup; the guide B table again when the instance changes)
   for (int j = threadIdx.x; j < N; j += WG) {
-    s_tw[j] = a.tw[j];
+    if (j < TWN) s_tw[j] = a.tw[j];
     if constexpr (KZ) s_kz[j] = a.kt[2][j];
   }
   const double pre_scale = (CONTIG && (a.pre & PRE_SCALE)) ? *a.scale : 1.0;
