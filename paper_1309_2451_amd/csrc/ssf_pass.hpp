@@ -115,7 +115,7 @@ template <int N> struct Shape {
   static constexpr bool v1(int dt) { return sx0(dt) > 1; }
   static constexpr int sx(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sx0(dt) / 2 : sx0(dt); }
   static constexpr int sm(int dt, int var = 0) { return sm0(dt); }
-  static constexpr int ldrow() { return N + N / 8 + (N >= 8 ? 0 : 0); }
+  static constexpr int ldrow() { return N; }
   static constexpr int cr() {              // contiguous rows per workgroup
     int rows = 256 * E / N;
     if (SSF_CR_SHIFT > 0) rows <<= SSF_CR_SHIFT;
@@ -341,13 +341,11 @@ __device__ __forceinline__ void sincos_fast(double t, double* s, double* c) {
   *s = sgn_s * (swap ? cr : sr);
   *c = sgn_c * (swap ? sr : cr);
 }
-// exp(-i theta) for |theta| <= pi/4 (no reduction needed): Taylor series of
-// sin to degree 15 and of cos to degree 16, truncation error below 5e-17
-// (LOW: degree 11 and 12).
-template <bool LOW = false>
-__device__ __forceinline__ double2 phase_small(double r) {
+// exp(-i theta) without argument reduction, Taylor series from the term
+// index S0 of sin and C0 of cos (see SINCOS_C).
+template <int S0, int C0>
+__device__ __forceinline__ double2 phase_series(double r) {
   const double r2 = r * r;
-  constexpr int S0 = LOW ? 3 : 1, C0 = LOW ? 11 : 9;
   double ps = SINCOS_C[S0];
 #pragma unroll
   for (int k = S0 + 1; k < 8; ++k) ps = fma(ps, r2, SINCOS_C[k]);
@@ -357,6 +355,18 @@ __device__ __forceinline__ double2 phase_small(double r) {
   for (int k = C0 + 1; k < 17; ++k) pc = fma(pc, r2, SINCOS_C[k]);
   const double cr = fma(-pc, r2, 1.0);
   return make_double2(cr, -sr);
+}
+// |theta| <= pi/4: sin to degree 15 and cos to degree 16, truncation error
+// below 5e-17 (LOW: degree 11 and 12, below 7e-12).
+template <bool LOW = false>
+__device__ __forceinline__ double2 phase_small(double r) {
+  return phase_series<LOW ? 3 : 1, LOW ? 11 : 9>(r);
+}
+// |theta| <= 0.1: sin to degree 9 and cos to degree 10, truncation error
+// below 3e-19 (LOW: degree 5 and 6, below 3e-11).
+template <bool LOW = false>
+__device__ __forceinline__ double2 phase_tiny(double r) {
+  return phase_series<LOW ? 6 : 4, LOW ? 14 : 12>(r);
 }
 // exp(-i theta)
 template <bool LOW = false>
@@ -467,7 +477,10 @@ struct PassGeom {
     }
   }
   __device__ static __forceinline__ int lidx(int b, int n) {
-    if constexpr (CONTIG) return b * LDROW + n + (n >> 3);
+    // rows are swizzled (n XOR bits 3..6 of n, a permutation of every
+    // supported length) so that the strided stage writes of 16 lanes fall
+    // into distinct bank sets
+    if constexpr (CONTIG) return b * LDROW + (n ^ ((n >> 3) & 15));
     else return n * P + b;
   }
 };
@@ -858,7 +871,10 @@ pass_kernel(PassArgs a) {
                 V[u * rm + m] = ctap ? -(s_A[x] * b0 + s_A[N + x] * b1 + s_A[2 * N + x] * b2) : 0.0;
               }
             }
-            if (a.small_phase) {
+            if (a.small_phase == 2) {
+#pragma unroll
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_tiny<LOWP>(V[e] * a.cmid));
+            } else if (a.small_phase == 1) {
 #pragma unroll
               for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_small<LOWP>(V[e] * a.cmid));
             } else {

@@ -303,7 +303,7 @@ struct ssf_handle {
   const void* vtab = nullptr;
   double* ctap = nullptr;              // A | D | B
   int nguides = 0;
-  double vmax = 0.0;                   // bound on |V| for the guide potential (sum of |v0|)
+  double vmax = 0.0;                   // bound on |V| for the guide potential
   int ix_lo = -1, ix_hi = 1 << 30;     // default: everything in P2
   int fuse = 1;
   int var[3] = {0, 0, 0};              // strided tile variant per axis (autotuned)
@@ -324,7 +324,9 @@ long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 // Guide tables on the host, FP64: A_g(x, z), D_g(x, z) = A_g (x - xc_g)/s_g^2
 // and B_g(y) for MAX_GUIDES guides (unused ones zero), the layout the pass
 // kernels read.
-void ctap_tables(const ssf_handle* h, const ssf_ctap_desc* d, std::vector<double>& tab) {
+// Returns a bound on |V| over the grid: max over (x, z) of sum_g |A_g(x, z)|
+// (every B_g(y) <= 1).
+double ctap_tables(const ssf_handle* h, const ssf_ctap_desc* d, std::vector<double>& tab) {
   // The kernels always evaluate MAX_GUIDES guides: unused ones get zero tables.
   const int nx = h->n[0], ny = h->n[1], nz = h->n[2], ng = d->nguides;
   const long long plane = (long long)ssf::MAX_GUIDES * nz * nx;
@@ -345,6 +347,22 @@ void ctap_tables(const ssf_handle* h, const ssf_ctap_desc* d, std::vector<double
       tab[2 * plane + (long long)g * ny + y] = std::exp(-yc * yc / (2.0 * s2));
     }
   }
+  double vmax = 0.0;
+  for (long long o = 0; o < (long long)nz * nx; ++o) {
+    double a = 0.0;
+    for (int g = 0; g < ng; ++g) a += std::fabs(tab[(long long)g * nz * nx + o]);
+    vmax = std::max(vmax, a);
+  }
+  return vmax;
+}
+
+// Which phase series the fused x pass may use for exp(-i V dt): 2 when
+// |V dt| <= 0.1, 1 when |V dt| <= 0.78 (inside pi/4), else 0 (reduction).
+int phase_tier(int vkind, double vmax, double dt) {
+  if (vkind == ssf::V_NONE) return 2;
+  if (vkind != ssf::V_CTAP) return 0;
+  const double t = vmax * std::fabs(dt);
+  return t <= 0.1 ? 2 : (t <= 0.78 ? 1 : 0);
 }
 
 // Partition of x into guide regions as integer bounds: P1 for x_i < x_lo,
@@ -761,13 +779,12 @@ ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d) {
   for (int g = 0; g < d->nguides; ++g)
     if (!(d->sigma[g] > 0.0) || !std::isfinite(d->v0[g])) return fail(SSF_E_INVALID, "sigma must be > 0, v0 finite");
   std::vector<double> tab;
-  ctap_tables(h, d, tab);
+  const double vmax = ctap_tables(h, d, tab);
   if (h->ctap) { HIP_TRY(hipStreamSynchronize(h->stream)); (void)hipFree(h->ctap); h->ctap = nullptr; }
   HIP_TRY(hipMalloc(&h->ctap, sizeof(double) * tab.size()));
   HIP_TRY(hipMemcpy(h->ctap, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
   h->nguides = d->nguides;
-  h->vmax = 0.0;
-  for (int g = 0; g < d->nguides; ++g) h->vmax += std::fabs(d->v0[g]);
+  h->vmax = vmax;
   h->vkind = ssf::V_CTAP;
   h->vtab = nullptr;
   return SSF_OK;
@@ -838,7 +855,7 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
       am.cmid = dt;
       am.imag = imag;
       // |V dt| <= pi/4 lets the phase skip its argument reduction
-      am.small_phase = (h->vkind == ssf::V_CTAP && h->vmax * std::fabs(dt) <= 0.78) || h->vkind == ssf::V_NONE;
+      am.small_phase = phase_tier(h->vkind, h->vmax, dt);
       SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
     }
   }
@@ -1122,7 +1139,7 @@ ssf_status batch_chunk(BatchGroup& G, int64_t k, double dt, const double2* kt) {
     if (s < k) {
       am.mid = ssf::MID_VPHASE;
       am.cmid = dt;
-      am.small_phase = G.vmax * std::fabs(dt) <= 0.78 ? 1 : 0;
+      am.small_phase = phase_tier(ssf::V_CTAP, G.vmax, dt);
       SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
     } else {
       am.post = ssf::POST_VPHASE;
@@ -1228,14 +1245,12 @@ ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf
       if (!(d->sigma[q] > 0.0) || !std::isfinite(d->v0[q])) return bail(fail(SSF_E_INVALID, "sigma must be > 0"));
     if (!(x_lo[i] <= x_hi[i])) return bail(fail(SSF_E_INVALID, "partition needs x_lo <= x_hi"));
     std::vector<double> tab;
-    ctap_tables(G.h, d, tab);
+    const double vm = ctap_tables(G.h, d, tab);
     double* dev = nullptr;
     if (hipMalloc(&dev, sizeof(double) * tab.size()) != hipSuccess) return bail(fail(SSF_E_NOMEM, "guide tables"));
     G.ctap.push_back(dev);
     if (hipMemcpy(dev, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(SSF_E_DEVICE, "guide table upload"));
-    double vm = 0.0;
-    for (int q = 0; q < d->nguides; ++q) vm += std::fabs(d->v0[q]);
     G.vmax = std::max(G.vmax, vm);
     ssf::InstDesc id;
     id.in = nullptr;
