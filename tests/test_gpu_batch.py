@@ -146,3 +146,38 @@ def test_batch_single_instance_ragged_grid_and_errors():
         ssf.Batch([(g.n, g.lo, g.hi)], [(gd.v0, (0.6, -1.0, 0.6), gd.xc)], [gd.x_lo], [gd.x_hi], dtype="c64")
     with pytest.raises(ssf.SSFError):
         ssf.Batch([((24, 20, 7), g.lo, g.hi)], [(gd.v0, gd.sigma, np.zeros((3, 7)))], [0.0], [0.0], dtype="c64")
+
+
+def test_batch_sweep_full_size_instances_vs_oracle():
+    """One instance of each grid size of the 96-instance sweep (seeded) at its
+    full size, run as one batch in complex128 for 6 steps in chunks of 4
+    (a remainder of 2 run eagerly, then one graph replay), against
+    the oracle instance by instance."""
+    cfg = synth.config4()
+    picked, seen = [], set()
+    for it in cfg["instances"]:
+        if it["grid"].n not in seen:
+            seen.add(it["grid"].n)
+            picked.append(it)
+    inst = []
+    for it in picked:
+        g, gd = it["grid"], it["guides"]
+        psi = synth.gaussian_packet(g, centre=(gd.xc[0, 0], 0.0, it["z0"]), width=(0.5, 0.5, it["zwidth"]),
+                                    k=(0.0, 0.0, it["kz"]))
+        inst.append((g, gd, psi))
+    b = _batch(inst, "c128")
+    assert b.groups()[0] == len(inst)
+    fields = [torch.from_numpy(p).to(DEV).contiguous() for _, _, p in inst]
+    obs = b.obs_buffer()
+    dt = cfg["dt"]
+    b.run(fields, 6, dt, chunk=4, obs_buf=obs)
+    rec = b.read_obs(obs)
+    for i, (g, gd, psi) in enumerate(inst):
+        say("sweep instance", g.n)
+        V = oracle.ctap_potential(g.shape, g.lo, g.hi, gd.v0, gd.sigma, gd.xc)
+        ref, _ = oracle.step(psi, V, g.lo, g.hi, dt, 6)
+        assert np.linalg.norm(fields[i].cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-12, g.n
+        o = oracle.observables(ref, V, g.lo, g.hi, gd.x_lo, gd.x_hi)
+        assert abs(rec[i]["norm"] - o["norm"]) < 1e-12
+        assert abs(rec[i]["pop"][0] - o["p1"]) < 1e-12
+    b.close()

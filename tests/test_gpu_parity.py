@@ -459,3 +459,58 @@ def test_zero_steps_and_sparse_observations():
     with pytest.raises(ssf.SSFError):
         s.step(t, 1, float("nan"))
     s.close()
+
+
+def test_full_size_512_cube_vs_oracle():
+    """The 512^3 workload (seeded +-5 % guides) in complex64 at its full size,
+    tuned tiles, fused chain: two steps against the oracle."""
+    say("512^3 workload c64")
+    cfg = synth.config3()
+    g, gd = cfg["grid"], cfg["guides"]
+    psi0 = c64_round(synth.gaussian_packet(g, centre=(gd.xc[0, 0], 0.0, cfg["z0"]), width=(0.4, 0.4, cfg["zwidth"]),
+                                           k=(0.0, 0.0, cfg["kz"])))
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    s.set_guides(gd.v0, gd.sigma, gd.xc)
+    s.set_partition(gd.x_lo, gd.x_hi)
+    s.tune(reps=2)
+    t = to_dev(psi0, s)
+    n = 2
+    s.step(t, n, cfg["dt"])
+    V = oracle.ctap_potential(g.shape, g.lo, g.hi, gd.v0, gd.sigma, gd.xc)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, cfg["dt"], n)
+    del V
+    err = rel(host(t), ref)
+    say("rel L2", err)
+    assert err < 3 * 6e-8 * np.sqrt(4 * n + 2)
+    s.close()
+
+
+def test_gradient_workload_full_size_vs_oracle_adjoint():
+    """The gradient workload at its full size (128 x 128 x 256, 2 x 16 B-spline
+    coefficients) in complex128 through the autograd function, 24 steps with
+    checkpoints every 8, against the oracle's stored-state adjoint."""
+    say("gradient workload full size")
+    from paper_1309_2451_amd.fidelity import FidelityFn, FidelityProblem
+    cfg = synth.config5()
+    g = cfg["grid"]
+    a, b = cfg["zrange"]
+    M, dt, n = cfg["M"], cfg["dt"], 24
+    # a packet straddling the target-guide boundary, so that F and its gradient are O(1e-1)
+    psi0 = synth.gaussian_packet(g, centre=(0.8, 0.0, -8.0), width=(1.0, 0.8, 3.0), k=(0.0, 0.0, 3.0))
+    s = ssf.Solver(g.n, g.lo, g.hi, "c128")
+    prob = FidelityProblem(s, to_dev(psi0, s), cfg["v0"], cfg["sigma"], np.zeros(g.n[2]), M, (a, b),
+                           cfg["x_lo"], cfg["x_hi"], dt, n, 8)
+    c = torch.tensor(cfg["coeffs"], dtype=torch.float64, requires_grad=True)
+    F = FidelityFn.apply(c, prob)
+    F.backward()
+    grad = c.grad.numpy()
+    xc = prob.profile(cfg["coeffs"])
+    F_ref, G_ref, _ = oracle.adjoint_ctap(psi0, g.lo, g.hi, cfg["v0"], cfg["sigma"], xc, dt, n, cfg["x_hi"])
+    Bo = oracle.bspline_basis(M, a, b, g.axis(2))
+    grad_ref = np.stack([G_ref[0] @ Bo, G_ref[2] @ Bo])
+    scale = np.max(np.abs(grad_ref))
+    say("F", float(F.detach()), F_ref, "max|grad|", scale)
+    assert F_ref > 1e-2 and scale > 1e-4
+    assert abs(float(F.detach()) - F_ref) < 1e-12
+    assert np.max(np.abs(grad - grad_ref)) < 1e-9 * scale
+    s.close()
