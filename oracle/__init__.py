@@ -19,6 +19,11 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                              phase after 10^4 steps, norm conservation
   step (imaginary time)      pinned: Strang fixed-point Gaussian width and per-step
                              norm ratio (closed forms)
+  step, order "tvt"          pinned: brute-force 8^3 T/2-V-T/2 step, exact discrete
+                             mean position and momentum of a displaced Gaussian in a
+                             harmonic trap (both orders: same <x>, different <p>),
+                             free-particle identity with "vtv", second-order
+                             convergence of both orders to the continuum coherent state
   observables                pinned: closed-form moments of Gaussians, <H> of
                              harmonic-oscillator eigenstates
   ctap_potential             pinned: special cases (isolated guide minimum -v0,
@@ -66,6 +71,8 @@ def _load():
         lib.orc_kgrid.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         lib.orc_step.argtypes = [dp, dp, ip, dp, dp, ctypes.c_double, ctypes.c_long,
                                  ctypes.c_int, dp]
+        lib.orc_step_order.argtypes = [dp, dp, ip, dp, dp, ctypes.c_double, ctypes.c_long,
+                                       ctypes.c_int, dp, ctypes.c_int]
         lib.orc_observables.argtypes = [dp, dp, ip, dp, dp, ctypes.c_double,
                                         ctypes.c_double, dp]
         lib.orc_ctap_potential.argtypes = [dp, ip, dp, dp, ctypes.c_int, dp, dp, dp]
@@ -136,17 +143,19 @@ def _grid_from(shape_zyx, lo, hi):
     return _grid_args([nx, ny, nz], lo, hi)
 
 
-def step(psi, V, lo, hi, dt, nsteps, imag=False):
-    """nsteps Strang steps V/2-T-V/2.  Returns (psi, edecay) where edecay is the
-    per-step -ln(norm ratio)/dt in imaginary time (None in real time)."""
+def step(psi, V, lo, hi, dt, nsteps, imag=False, order="vtv"):
+    """nsteps Strang steps, order "vtv" (V/2-T-V/2) or "tvt" (T/2-V-T/2).
+    Returns (psi, edecay) where edecay is the per-step -ln(norm ratio)/dt in
+    imaginary time (None in real time)."""
     a = _c128(psi)
     n, lo, hi = _grid_from(a.shape, lo, hi)
     Va = None if V is None else np.ascontiguousarray(V, dtype=np.float64)
     if Va is not None:
         assert Va.shape == a.shape
     ed = np.zeros(max(int(nsteps), 1), dtype=np.float64) if imag else None
-    _load().orc_step(_as_dp_complex(a), _dp(Va), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                     _dp(lo), _dp(hi), float(dt), int(nsteps), 1 if imag else 0, _dp(ed))
+    _load().orc_step_order(_as_dp_complex(a), _dp(Va), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           _dp(lo), _dp(hi), float(dt), int(nsteps), 1 if imag else 0, _dp(ed),
+                           {"vtv": 0, "tvt": 1}[order])
     return a, (ed[:int(nsteps)] if imag else None)
 
 

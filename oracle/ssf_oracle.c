@@ -259,15 +259,34 @@ static void one_step(cplx *psi, const double *V, const grid_t *g, double dt, int
 }
 
 /*
- * nsteps Strang steps.  Real time (imag = 0): no renormalisation.
+ * The other symmetric ordering, T/2 - V - T/2 (Sec. IV counts four Fourier
+ * transforms and three multiplications per step, which is this form taken
+ * step by step): half a kinetic step in momentum space, the full potential
+ * phase in position space, half a kinetic step again.
+ */
+static void one_step_tvt(cplx *psi, const double *V, const grid_t *g, double dt, int imag)
+{
+    long tot = grid_points(g);
+    fft3d(psi, g->n[0], g->n[1], g->n[2], -1);
+    kinetic_full(psi, g, 0.5 * dt, imag);
+    fft3d(psi, g->n[0], g->n[1], g->n[2], +1);
+    potential_half(psi, V, tot, 2.0 * dt, imag);
+    fft3d(psi, g->n[0], g->n[1], g->n[2], -1);
+    kinetic_full(psi, g, 0.5 * dt, imag);
+    fft3d(psi, g->n[0], g->n[1], g->n[2], +1);
+}
+
+/*
+ * nsteps Strang steps, order 0 = V/2 - T - V/2, 1 = T/2 - V - T/2.
+ * Real time (imag = 0): no renormalisation.
  * Imaginary time (imag = 1): after every step psi is rescaled to
  * sum |psi|^2 dV = 1 and, if edecay != NULL, edecay[s] receives
  * -ln(||psi_{s+1}|| / ||psi_s||) / dt measured before the rescale (the
  * input is taken as it is, so edecay[0] assumes a normalised input).
  * V may be NULL (free particle).
  */
-void orc_step(double *psi_, const double *V, const int *n, const double *lo, const double *hi,
-              double dt, long nsteps, int imag, double *edecay)
+void orc_step_order(double *psi_, const double *V, const int *n, const double *lo, const double *hi,
+                    double dt, long nsteps, int imag, double *edecay, int order)
 {
     grid_t g = make_grid(n, lo, hi);
     cplx *psi = (cplx *)psi_;
@@ -275,7 +294,8 @@ void orc_step(double *psi_, const double *V, const int *n, const double *lo, con
     double dv = grid_dv(&g);
     double prev = sqrt(sum_abs2(psi, tot) * dv);
     for (long s = 0; s < nsteps; ++s) {
-        one_step(psi, V, &g, dt, imag);
+        if (order == 1) one_step_tvt(psi, V, &g, dt, imag);
+        else one_step(psi, V, &g, dt, imag);
         if (imag) {
             double nrm = sqrt(sum_abs2(psi, tot) * dv);
             if (edecay) edecay[s] = -log(nrm / prev) / dt;
@@ -284,6 +304,12 @@ void orc_step(double *psi_, const double *V, const int *n, const double *lo, con
             prev = 1.0;
         }
     }
+}
+
+void orc_step(double *psi_, const double *V, const int *n, const double *lo, const double *hi,
+              double dt, long nsteps, int imag, double *edecay)
+{
+    orc_step_order(psi_, V, n, lo, hi, dt, nsteps, imag, edecay, 0);
 }
 
 /* ------------------------------------------------------------------------ */
