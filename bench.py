@@ -35,6 +35,8 @@ Further sections (each can be skipped with --sections):
   c3       512^3, seeded +-5 % guide parameters, 500 imaginary-time steps on
            the full grid, then 5000 real-time steps in complex64 and
            complex128.
+  tvt      the headline workload in the T/2 - V - T/2 ordering (complex64,
+           --tvt-steps steps): rate and distance from the V/2 - T - V/2 run.
 """
 from __future__ import annotations
 
@@ -51,7 +53,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point split-step updates/s + HBM GB/s vs roofline, c64 vs c128 at ≤1e-4 L2"
-ALL_SECTIONS = ("c128", "cpu", "batch", "adjoint", "c3")
+ALL_SECTIONS = ("c128", "cpu", "batch", "adjoint", "c3", "tvt")
 
 
 def log(*a):
@@ -99,9 +101,11 @@ def c2_initial_state(torch, ssf, cfg, device):
 # ---------------------------------------------------------------------------
 # one timed run of a single field
 # ---------------------------------------------------------------------------
-def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tune=True, timing=True):
+def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tune=True, timing=True,
+              splitting="vtv"):
     g, gd = cfg["grid"], cfg["guides"]
     s = ssf.Solver(g.n, g.lo, g.hi, dtype, device=device)
+    s.set_splitting(splitting)
     s.set_guides(gd.v0, gd.sigma, gd.xc)
     s.set_partition(gd.x_lo, gd.x_hi)
     tune_info = None
@@ -428,6 +432,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=None)
     ap.add_argument("--adjoint-steps", type=int, default=None)
     ap.add_argument("--c3-steps", type=int, default=None)
+    ap.add_argument("--tvt-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the library's plain field copy (2 x field bytes per launch), which "
                          "calibrates profiler byte counters")
@@ -532,6 +537,16 @@ def main():
     del r64
     torch.cuda.empty_cache()
 
+    if "tvt" in sections:
+        log("tvt: T/2-V-T/2 ordering, c64, %d steps" % a.tvt_steps)
+        rt = timed_run(torch, ssf, cfg, psi0, "c64", a.tvt_steps, 20, a.obs_every, device, splitting="tvt")
+        rv = timed_run(torch, ssf, cfg, psi0, "c64", a.tvt_steps, 0, a.obs_every, device, timing=False)
+        out["tvt"] = {"value": g.points * a.tvt_steps / (rt["ms"] * 1e-3), "ms_per_step": rt["ms"] / a.tvt_steps,
+                      "steps": a.tvt_steps, "passes": pass_summary(rt["passes"]),
+                      "rel_l2_vs_vtv": rel_l2(torch, rt["psi"], rv["psi"]),
+                      "norm_drift": float(rt["rec"][-1]["norm"] - 1.0) if rt["rec"] is not None else None}
+        del rt, rv
+        torch.cuda.empty_cache()
     if "batch" in sections:
         out["batch"] = section_batch(torch, ssf, device, steps=a.batch_steps)
         torch.cuda.empty_cache()

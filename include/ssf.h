@@ -64,6 +64,8 @@ typedef int32_t ssf_status;
 #define SSF_C128 2
 #define SSF_REAL 0
 #define SSF_IMAG 1
+#define SSF_SPLIT_VTV 0
+#define SSF_SPLIT_TVT 1
 
 typedef struct ssf_handle ssf_handle;
 
@@ -122,6 +124,16 @@ ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi);
  * and the next forward x transform), 4 passes per step.  Same result up to
  * rounding. */
 ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
+/* Ordering of the symmetric split step taken by ssf_step in real time:
+ * SSF_SPLIT_VTV (default) = exp(-iV dt/2) exp(-iT dt) exp(-iV dt/2);
+ * SSF_SPLIT_TVT = exp(-iT dt/2) exp(-iV dt) exp(-iT dt/2), the ordering whose
+ * per-step count is four Fourier transforms and three multiplications
+ * (Sec. IV).  Both are second order.  With TVT consecutive steps share the
+ * kinetic passes (steady state: 4 passes per step, like VTV); each chain
+ * start and each observation add a half-kinetic y/z round trip.  Imaginary
+ * time, ssf_step_ckpt, ssf_step_seq and the adjoint use VTV only and return
+ * SSF_E_UNSUPPORTED while TVT is selected. */
+ssf_status ssf_set_splitting(ssf_handle* h, int32_t order);
 
 /* Tile autotuner.  The y and z passes come in NUM variants of tile shape
  * (0: 128 B of storage per row segment; 1: half-width tile, half the

@@ -140,6 +140,10 @@ class Solver:
     def set_fusion(self, on: bool):
         _ssf.call("ssf_set_fusion", self.h, 1 if on else 0)
 
+    def set_splitting(self, order: str):
+        """"vtv" (default: V/2-T-V/2) or "tvt" (T/2-V-T/2) for real-time steps."""
+        _ssf.call("ssf_set_splitting", self.h, {"vtv": _ssf.SSF_SPLIT_VTV, "tvt": _ssf.SSF_SPLIT_TVT}[order])
+
     def tune(self, reps=5):
         """Time every y/z tile variant on this grid and keep the fastest.
         Returns (choice[3], {(axis, variant): microseconds})."""

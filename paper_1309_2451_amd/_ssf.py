@@ -27,11 +27,13 @@ SSF_C64 = 1
 SSF_C128 = 2
 SSF_REAL = 0
 SSF_IMAG = 1
+SSF_SPLIT_VTV = 0
+SSF_SPLIT_TVT = 1
 
 EXPORTS = (
     "ssf_supported_length", "ssf_create", "ssf_destroy", "ssf_set_stream",
     "ssf_set_potential_table", "ssf_set_potential_ctap", "ssf_clear_potential",
-    "ssf_set_partition", "ssf_set_fusion", "ssf_set_timing", "ssf_timing_read",
+    "ssf_set_partition", "ssf_set_fusion", "ssf_set_splitting", "ssf_set_timing", "ssf_timing_read",
     "ssf_tune", "ssf_set_tiles", "ssf_get_tiles", "ssf_step", "ssf_fft", "ssf_observables",
     "ssf_obs_read", "ssf_sync", "ssf_copy", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
@@ -95,6 +97,7 @@ def load():
         "ssf_clear_potential": ([hp], i32),
         "ssf_set_partition": ([hp, dbl, dbl], i32),
         "ssf_set_fusion": ([hp, i32], i32),
+        "ssf_set_splitting": ([hp, i32], i32),
         "ssf_set_timing": ([hp, i32], i32),
         "ssf_tune": ([hp, i32, vp, vp], i32),
         "ssf_set_tiles": ([hp, vp], i32),

@@ -306,6 +306,7 @@ struct ssf_handle {
   double vmax = 0.0;                   // bound on |V| for the guide potential
   int ix_lo = -1, ix_hi = 1 << 30;     // default: everything in P2
   int fuse = 1;
+  int split = SSF_SPLIT_VTV;           // ordering of ssf_step in real time
   int var[3] = {0, 0, 0};              // strided tile variant per axis (autotuned)
   double* partials = nullptr;          // workspace: 2 regions of part_cap blocks x 8 doubles
   long long part_cap = 0;
@@ -757,6 +758,13 @@ ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps) {
   return SSF_OK;
 }
 
+ssf_status ssf_set_splitting(ssf_handle* h, int32_t order) {
+  SSF_TRY(check_handle(h));
+  if (order != SSF_SPLIT_VTV && order != SSF_SPLIT_TVT) return fail(SSF_E_INVALID, "unknown splitting order");
+  h->split = order;
+  return SSF_OK;
+}
+
 ssf_status ssf_set_potential_table(ssf_handle* h, const void* v_dev, int32_t v_is_f64) {
   SSF_TRY(check_handle(h));
   if (!v_dev) return fail(SSF_E_INVALID, "potential table is null");
@@ -863,6 +871,44 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
   return SSF_OK;
 }
 
+// Real-time steps in the T/2 - V - T/2 ordering.  A chain is x forward, a
+// half kinetic step (y, z-fused, y), then per step the fused x pass with
+// exp(-i V dt) followed by a full kinetic step, except that the last step of
+// the chain ends with a half kinetic step and the x inverse (with the
+// observation reduction when one is due).  The 1/N of the unnormalised
+// transforms is in every z kinetic table, full or half, one per x round trip.
+static ssf_status run_steps_tvt(ssf_handle* h, void* psi, int64_t nsteps, double dt, int64_t obs_every,
+                                ssf_obs* obs_dev) {
+  const double2 *kt = nullptr, *kh = nullptr;
+  SSF_TRY(get_ktab(h, dt, 0, &kt));
+  SSF_TRY(get_ktab(h, 0.5 * dt, 0, &kh));
+  int64_t s = 0;
+  while (s < nsteps) {
+    PassArgs ax = base_args(h, psi, psi, 0);
+    SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
+    SSF_TRY(step_middle(h, psi, kh));
+    for (;;) {
+      PassArgs am = base_args(h, psi, psi, 0);
+      am.mid = ssf::MID_VPHASE;
+      am.cmid = dt;
+      am.small_phase = phase_tier(h->vkind, h->vmax, dt);
+      SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
+      ++s;
+      const bool obs_due = obs_every > 0 && obs_dev && (s % obs_every) == 0;
+      if (!h->fuse || s == nsteps || obs_due) {
+        SSF_TRY(step_middle(h, psi, kh));
+        PassArgs ai = base_args(h, psi, psi, 0);
+        ai.post = obs_due ? ssf::POST_OBS : 0;
+        SSF_TRY(launch(h, ssf::CONTIG_INV, 0, ai));
+        if (obs_due) SSF_TRY(finalize_obs(h, obs_dev + (s / obs_every - 1), s, 1, dt, nullptr, 0));
+        break;
+      }
+      SSF_TRY(step_middle(h, psi, kt));
+    }
+  }
+  return SSF_OK;
+}
+
 ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time, int64_t obs_every,
                     ssf_obs* obs_dev) {
   SSF_TRY(check_handle(h));
@@ -873,6 +919,10 @@ ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t
   if (time == SSF_IMAG && dt < 0.0) return fail(SSF_E_INVALID, "imaginary time needs dt > 0");
   if (obs_every < 0) return fail(SSF_E_INVALID, "obs_every must be >= 0");
   if (nsteps == 0) return SSF_OK;
+  if (h->split == SSF_SPLIT_TVT) {
+    if (time == SSF_IMAG) return fail(SSF_E_UNSUPPORTED, "imaginary time uses the V/2-T-V/2 ordering");
+    return run_steps_tvt(h, psi, nsteps, dt, obs_every, obs_dev);
+  }
   return run_steps(h, psi, psi, nsteps, dt, time == SSF_IMAG ? 1 : 0, obs_every, obs_dev, true);
 }
 
@@ -933,6 +983,7 @@ ssf_status ssf_copy(ssf_handle* h, const void* src, void* dst) {
 
 ssf_status ssf_step_ckpt(ssf_handle* h, void* psi, int64_t nsteps, double dt, int64_t every, void* ckpt_dev) {
   SSF_TRY(check_handle(h));
+  if (h->split != SSF_SPLIT_VTV) return fail(SSF_E_UNSUPPORTED, "checkpoints and the adjoint use the V/2-T-V/2 ordering");
   SSF_TRY(check_field(h, psi, "psi"));
   SSF_TRY(check_field(h, ckpt_dev, "ckpt_dev"));
   if (nsteps < 0 || every < 1) return fail(SSF_E_INVALID, "need nsteps >= 0 and every >= 1");
@@ -947,6 +998,7 @@ ssf_status ssf_step_ckpt(ssf_handle* h, void* psi, int64_t nsteps, double dt, in
 
 ssf_status ssf_step_seq(ssf_handle* h, const void* psi0, int64_t nsteps, double dt, void* seq_dev) {
   SSF_TRY(check_handle(h));
+  if (h->split != SSF_SPLIT_VTV) return fail(SSF_E_UNSUPPORTED, "checkpoints and the adjoint use the V/2-T-V/2 ordering");
   SSF_TRY(check_field(h, psi0, "psi0"));
   SSF_TRY(check_field(h, seq_dev, "seq_dev"));
   if (nsteps < 0) return fail(SSF_E_INVALID, "nsteps must be >= 0");
@@ -977,6 +1029,7 @@ ssf_status ssf_adjoint_init(ssf_handle* h, const void* psi, void* lambda) {
 ssf_status ssf_adjoint_segment(ssf_handle* h, void* lambda, const void* seq_dev, int64_t nsteps, double dt,
                                double* G_dev) {
   SSF_TRY(check_handle(h));
+  if (h->split != SSF_SPLIT_VTV) return fail(SSF_E_UNSUPPORTED, "checkpoints and the adjoint use the V/2-T-V/2 ordering");
   SSF_TRY(check_field(h, lambda, "lambda"));
   SSF_TRY(check_field(h, seq_dev, "seq_dev"));
   if (!G_dev) return fail(SSF_E_INVALID, "G_dev is null");
