@@ -26,6 +26,10 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                              convergence of both orders to the continuum coherent state
   observables                pinned: closed-form moments of Gaussians, <H> of
                              harmonic-oscillator eigenstates
+  populations_z              pinned: constant boundaries reduce to observables'
+                             populations, brute force on a tiny grid, P1+P2+P3 = norm
+  density_xz                 pinned: closed-form Gaussian y-integral of a separable
+                             state, brute force on a tiny grid, total = norm
   ctap_potential             pinned: special cases (isolated guide minimum -v0,
                              value one sigma off-centre, y-symmetry)
   bspline_basis              pinned: partition of unity, linear precision with
@@ -76,6 +80,8 @@ def _load():
         lib.orc_observables.argtypes = [dp, dp, ip, dp, dp, ctypes.c_double,
                                         ctypes.c_double, dp]
         lib.orc_ctap_potential.argtypes = [dp, ip, dp, dp, ctypes.c_int, dp, dp, dp]
+        lib.orc_populations_z.argtypes = [dp, ip, dp, dp, dp, dp, dp]
+        lib.orc_density_xz.argtypes = [dp, ip, dp, dp, dp]
         lib.orc_bspline_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                           dp, ctypes.c_int, dp]
         lib.orc_adjoint_ctap.argtypes = [dp, ip, dp, dp, ctypes.c_int, dp, dp, dp,
@@ -172,6 +178,29 @@ def observables(psi, V, lo, hi, x_lo, x_hi):
                             n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(lo), _dp(hi),
                             float(x_lo), float(x_hi), _dp(out))
     return dict(zip(OBS_FIELDS, out.tolist()))
+
+
+def populations_z(psi, lo, hi, x_lo, x_hi):
+    """(P1, P2, P3) with plane-dependent boundaries x_lo[z], x_hi[z] (length Nz)."""
+    a = _c128(psi)
+    n, lo, hi = _grid_from(a.shape, lo, hi)
+    xl = np.ascontiguousarray(x_lo, dtype=np.float64)
+    xh = np.ascontiguousarray(x_hi, dtype=np.float64)
+    assert xl.shape == (a.shape[0],) and xh.shape == (a.shape[0],)
+    out = np.zeros(3, dtype=np.float64)
+    _load().orc_populations_z(_as_dp_complex(a), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(lo), _dp(hi),
+                              _dp(xl), _dp(xh), _dp(out))
+    return tuple(out.tolist())
+
+
+def density_xz(psi, lo, hi):
+    """(Nz, Nx) density integrated over y: sum_y |psi|^2 dy."""
+    a = _c128(psi)
+    n, lo, hi = _grid_from(a.shape, lo, hi)
+    out = np.zeros((a.shape[0], a.shape[2]), dtype=np.float64)
+    _load().orc_density_xz(_as_dp_complex(a), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(lo), _dp(hi),
+                           _dp(out))
+    return out
 
 
 def ctap_potential(shape_zyx, lo, hi, v0, sigma, xc):

@@ -372,6 +372,54 @@ void orc_observables(const double *psi_, const double *V, const int *n, const do
     out[7] = kin * dv / (double)tot + s[7] * dv;
 }
 
+/*
+ * Guide populations with plane-dependent boundaries (Sec. V, Fig. 4: the
+ * population of each waveguide as the guides move): out[0] = P1 = sum over
+ * x < x_lo[z], out[2] = P3 = sum over x > x_hi[z], out[1] = P2 the rest,
+ * each times dV.
+ */
+void orc_populations_z(const double *psi_, const int *n, const double *lo, const double *hi,
+                       const double *x_lo, const double *x_hi, double *out)
+{
+    grid_t g = make_grid(n, lo, hi);
+    const cplx *psi = (const cplx *)psi_;
+    int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    double dv = grid_dv(&g);
+    double p[3] = {0.0, 0.0, 0.0};
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double xc = grid_coord(&g, 0, x);
+                long i = ((long)z * ny + y) * nx + x;
+                double r = creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
+                if (xc < x_lo[z]) p[0] += r;
+                else if (xc > x_hi[z]) p[2] += r;
+                else p[1] += r;
+            }
+    for (int q = 0; q < 3; ++q) out[q] = p[q] * dv;
+}
+
+/*
+ * Density in the x-z plane integrated over y (Sec. V, Fig. 5):
+ * out[z * nx + x] = sum_y |psi(x, y, z)|^2 dy.
+ */
+void orc_density_xz(const double *psi_, const int *n, const double *lo, const double *hi, double *out)
+{
+    grid_t g = make_grid(n, lo, hi);
+    const cplx *psi = (const cplx *)psi_;
+    int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    double dy = (g.hi[1] - g.lo[1]) / ny;
+    for (int z = 0; z < nz; ++z)
+        for (int x = 0; x < nx; ++x) {
+            double s = 0.0;
+            for (int y = 0; y < ny; ++y) {
+                long i = ((long)z * ny + y) * nx + x;
+                s += creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
+            }
+            out[(long)z * nx + x] = s * dy;
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Three-guide potential (Gaussian stand-in for the chip's waveguides).      */
 /* ------------------------------------------------------------------------ */
