@@ -119,6 +119,12 @@ ssf_status ssf_clear_potential(ssf_handle* h);
 /* Guide regions for the populations: P1 counts grid points with x < x_lo,
  * P3 those with x > x_hi (strict), P2 the rest. */
 ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi);
+/* Plane-dependent guide regions (Sec. V, Fig. 4: the population of each guide
+ * while the guides move): x_lo[z], x_hi[z] for z = 0 .. Nz-1 (host arrays,
+ * copied; e.g. the midlines between neighbouring guide centres).  Used by
+ * every population until the next ssf_set_partition, including the target
+ * mask of ssf_adjoint_init.  Synchronises the handle's stream. */
+ssf_status ssf_set_partition_z(ssf_handle* h, const double* x_lo, const double* x_hi);
 /* 0: one Strang step = 5 passes; 1 (default): consecutive steps without an
  * observation between them share one x pass (exp(-i V dt) between the inverse
  * and the next forward x transform), 4 passes per step.  Same result up to
@@ -177,6 +183,10 @@ ssf_status ssf_observables(ssf_handle* h, const void* psi, ssf_obs* obs_dev);
 /* Copy count observations to the host (synchronises the stream).  Returns
  * SSF_E_NONFINITE if any copied record has flags bit 0 set. */
 ssf_status ssf_obs_read(ssf_handle* h, const ssf_obs* obs_dev, ssf_obs* host, int64_t count);
+/* Density in the x-z plane integrated over y (Sec. V, Fig. 5):
+ * out_dev[z * Nx + x] = sum_y |psi(x, y, z)|^2 dy, FP64, (Nz, Nx) device array,
+ * summed in a fixed order. */
+ssf_status ssf_density_xz(ssf_handle* h, const void* psi, double* out_dev);
 /* Wait for the handle's stream; reports pending asynchronous errors. */
 ssf_status ssf_sync(ssf_handle* h);
 /* dst = src for one field of the handle (storage type, layout as above), by a

@@ -137,6 +137,27 @@ class Solver:
     def set_partition(self, x_lo, x_hi):
         _ssf.call("ssf_set_partition", self.h, float(x_lo), float(x_hi))
 
+    def set_partition_z(self, x_lo, x_hi):
+        """Plane-dependent guide regions: arrays of length Nz."""
+        xl = np.ascontiguousarray(x_lo, dtype=np.float64)
+        xh = np.ascontiguousarray(x_hi, dtype=np.float64)
+        if xl.shape != (self.n[2],) or xh.shape != (self.n[2],):
+            raise ValueError("x_lo and x_hi must have length Nz = %d" % self.n[2])
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._sync_stream()
+        _ssf.call("ssf_set_partition_z", self.h, xl.ctypes.data_as(dp), xh.ctypes.data_as(dp))
+
+    def density_xz(self, psi, out=None):
+        """(Nz, Nx) float64 tensor: sum over y of |psi|^2 dy."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.n[2], self.n[0]), dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or tuple(out.shape) != (self.n[2], self.n[0]) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape (Nz, Nx)")
+        self._sync_stream()
+        _ssf.call("ssf_density_xz", self.h, self._field(psi), ctypes.c_void_p(out.data_ptr()))
+        return out
+
     def set_fusion(self, on: bool):
         _ssf.call("ssf_set_fusion", self.h, 1 if on else 0)
 

@@ -33,9 +33,9 @@ SSF_SPLIT_TVT = 1
 EXPORTS = (
     "ssf_supported_length", "ssf_create", "ssf_destroy", "ssf_set_stream",
     "ssf_set_potential_table", "ssf_set_potential_ctap", "ssf_clear_potential",
-    "ssf_set_partition", "ssf_set_fusion", "ssf_set_splitting", "ssf_set_timing", "ssf_timing_read",
+    "ssf_set_partition", "ssf_set_partition_z", "ssf_set_fusion", "ssf_set_splitting", "ssf_set_timing", "ssf_timing_read",
     "ssf_tune", "ssf_set_tiles", "ssf_get_tiles", "ssf_step", "ssf_fft", "ssf_observables",
-    "ssf_obs_read", "ssf_sync", "ssf_copy", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
+    "ssf_obs_read", "ssf_density_xz", "ssf_sync", "ssf_copy", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
     "ssf_batch_info", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
 )
@@ -96,6 +96,7 @@ def load():
         "ssf_set_potential_ctap": ([hp, ctypes.POINTER(ssf_ctap_desc)], i32),
         "ssf_clear_potential": ([hp], i32),
         "ssf_set_partition": ([hp, dbl, dbl], i32),
+        "ssf_set_partition_z": ([hp, dp, dp], i32),
         "ssf_set_fusion": ([hp, i32], i32),
         "ssf_set_splitting": ([hp, i32], i32),
         "ssf_set_timing": ([hp, i32], i32),
@@ -107,6 +108,7 @@ def load():
         "ssf_fft": ([hp, vp, i32, i32], i32),
         "ssf_observables": ([hp, vp, vp], i32),
         "ssf_obs_read": ([hp, vp, vp, i64], i32),
+        "ssf_density_xz": ([hp, vp, vp], i32),
         "ssf_sync": ([hp], i32),
         "ssf_copy": ([hp, vp, vp], i32),
         "ssf_step_ckpt": ([hp, vp, i64, dbl, i64, vp], i32),

@@ -63,6 +63,7 @@ struct PassArgs {
   double lo[3], d[3];      // grid origin and spacing
   double kfac[3];          // 2 pi / L per axis
   int ix_lo, ix_hi;        // P1: ix < ix_lo, P3: ix > ix_hi, P2 otherwise
+  const int* ixz;          // nullptr, or per plane z: (ix_lo, ix_hi) at [2z], [2z+1]
   int tiles_x, tiles_y;    // tile grid (set by the launcher); partial sums are per tile
   int small_phase;         // |V cmid| bound: 2: <= 0.1, 1: <= pi/4 (no argument reduction), 0: any
   const InstDesc* inst;    // batched launch: ninst instances of this grid (nullptr: single field)

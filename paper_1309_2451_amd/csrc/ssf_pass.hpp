@@ -916,6 +916,8 @@ pass_kernel(PassArgs a) {
         }
         if (a.post & POST_OBS) {
           const double zc = a.lo[2] + t1 * a.d[2];
+          const int ilo = a.ixz ? a.ixz[2 * t1] : a.ix_lo;
+          const int ihi = a.ixz ? a.ixz[2 * t1 + 1] : a.ix_hi;
 #pragma unroll
           for (int u = 0; u < E / r; ++u) {
             const double w = p.ok[u] ? 1.0 : 0.0;
@@ -929,9 +931,9 @@ pass_kernel(PassArgs a) {
               acc[1] += (a.lo[0] + n * a.d[0]) * rho;
               acc[2] += yc * rho;
               acc[3] += zc * rho;
-              acc[4] += n < a.ix_lo ? rho : 0.0;
-              acc[6] += n > a.ix_hi ? rho : 0.0;
-              acc[5] += (n >= a.ix_lo && n <= a.ix_hi) ? rho : 0.0;
+              acc[4] += n < ilo ? rho : 0.0;
+              acc[6] += n > ihi ? rho : 0.0;
+              acc[5] += (n >= ilo && n <= ihi) ? rho : 0.0;
               acc[7] += V[u * r + q] * rho;
             }
           }

@@ -171,6 +171,7 @@ __global__ void __launch_bounds__(256) obs_reduce_kernel(PassArgs a, int rows) {
   const int z = blockIdx.y, y0 = blockIdx.x * rows;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const S* in = (const S*)a.in;
+  const int ilo = a.ixz ? a.ixz[2 * z] : a.ix_lo, ihi = a.ixz ? a.ixz[2 * z + 1] : a.ix_hi;
   for (int e = threadIdx.x; e < rows * a.nx; e += 256) {
     const int y = y0 + e / a.nx, x = e % a.nx;
     if (y >= a.ny) break;
@@ -180,8 +181,8 @@ __global__ void __launch_bounds__(256) obs_reduce_kernel(PassArgs a, int rows) {
     acc[1] += (a.lo[0] + x * a.d[0]) * rho;
     acc[2] += (a.lo[1] + y * a.d[1]) * rho;
     acc[3] += (a.lo[2] + z * a.d[2]) * rho;
-    if (x < a.ix_lo) acc[4] += rho;
-    else if (x > a.ix_hi) acc[6] += rho;
+    if (x < ilo) acc[4] += rho;
+    else if (x > ihi) acc[6] += rho;
     else acc[5] += rho;
     acc[7] += ssf::potential_at(a, x, y, z) * rho;
   }
@@ -197,13 +198,14 @@ __global__ void scale_kernel(S* p, long long n, const double* scale) {
   }
 }
 
-// lambda = psi where x > x_hi (ix > ix_hi), 0 elsewhere.
+// lambda = psi where x > x_hi (ix > ix_hi, per plane if ixz is set), 0 elsewhere.
 template <typename S>
-__global__ void mask_kernel(const S* psi, S* lam, long long n, int nx, int ix_hi) {
+__global__ void mask_kernel(const S* psi, S* lam, long long n, int nx, long long nxy, int ix_hi, const int* ixz) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const int x = (int)(i % nx);
+    const int ihi = ixz ? ixz[2 * (i / nxy) + 1] : ix_hi;
     double2 v = ssf::ld2(psi + i);
-    if (x <= ix_hi) v = make_double2(0.0, 0.0);
+    if (x <= ihi) v = make_double2(0.0, 0.0);
     ssf::st2(lam + i, v);
   }
 }
@@ -272,6 +274,20 @@ __global__ void __launch_bounds__(256) copy_kernel(const S* in, S* out, long lon
   }
 }
 
+// out[z nx + x] = dy sum_y |psi(x, y, z)|^2, one thread per (x, z), fixed order.
+template <typename S>
+__global__ void __launch_bounds__(256) density_xz_kernel(const S* in, int nx, int ny, double dy, double* out) {
+  const int x = blockIdx.x * 256 + threadIdx.x, z = blockIdx.y;
+  if (x >= nx) return;
+  const S* p = in + (long long)z * ny * nx + x;
+  double s = 0.0;
+  for (int y = 0; y < ny; ++y) {
+    const double2 v = ssf::ld2(p + (long long)y * nx);
+    s += v.x * v.x + v.y * v.y;
+  }
+  out[(long long)z * nx + x] = s * dy;
+}
+
 // ---------------------------------------------------------------------------
 // Handle.
 // ---------------------------------------------------------------------------
@@ -307,6 +323,8 @@ struct ssf_handle {
   int ix_lo = -1, ix_hi = 1 << 30;     // default: everything in P2
   int fuse = 1;
   int split = SSF_SPLIT_VTV;           // ordering of ssf_step in real time
+  int* ixz = nullptr;                  // per-plane partition bounds (device, 2 nz)
+  int zpart = 0;                       // 1: ixz in use
   int var[3] = {0, 0, 0};              // strided tile variant per axis (autotuned)
   double* partials = nullptr;          // workspace: 2 regions of part_cap blocks x 8 doubles
   long long part_cap = 0;
@@ -428,6 +446,7 @@ PassArgs base_args(const ssf_handle* h, const void* in, void* out, int axis) {
   }
   a.ix_lo = h->ix_lo;
   a.ix_hi = h->ix_hi;
+  a.ixz = h->zpart ? h->ixz : nullptr;
   return a;
 }
 
@@ -641,6 +660,7 @@ ssf_status ssf_destroy(ssf_handle* h) {
   for (auto& k : h->kt) if (k.t) (void)hipFree(k.t);
   for (int a = 0; a < 3; ++a) if (h->tw[a]) (void)hipFree(h->tw[a]);
   if (h->ctap) (void)hipFree(h->ctap);
+  if (h->ixz) (void)hipFree(h->ixz);
   if (h->partials) (void)hipFree(h->partials);
   if (h->dscal) (void)hipFree(h->dscal);
   if (h->work) (void)hipFree(h->work);
@@ -805,6 +825,23 @@ ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi) {
   partition_indices(h, x_lo, x_hi, &ilo, &ihi);
   h->ix_lo = ilo;
   h->ix_hi = ihi;
+  h->zpart = 0;
+  return SSF_OK;
+}
+
+ssf_status ssf_set_partition_z(ssf_handle* h, const double* x_lo, const double* x_hi) {
+  SSF_TRY(check_handle(h));
+  if (!x_lo || !x_hi) return fail(SSF_E_INVALID, "null boundary arrays");
+  const int nz = h->n[2];
+  std::vector<int> ix(2 * (size_t)nz);
+  for (int z = 0; z < nz; ++z) {
+    if (!(x_lo[z] <= x_hi[z])) return fail(SSF_E_INVALID, "partition needs x_lo[z] <= x_hi[z]");
+    partition_indices(h, x_lo[z], x_hi[z], &ix[2 * z], &ix[2 * z + 1]);
+  }
+  if (!h->ixz) HIP_TRY(hipMalloc(&h->ixz, sizeof(int) * ix.size()));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(h->ixz, ix.data(), sizeof(int) * ix.size(), hipMemcpyHostToDevice));
+  h->zpart = 1;
   return SSF_OK;
 }
 
@@ -957,6 +994,21 @@ ssf_status ssf_obs_read(ssf_handle* h, const ssf_obs* obs_dev, ssf_obs* host, in
   return SSF_OK;
 }
 
+ssf_status ssf_density_xz(ssf_handle* h, const void* psi, double* out_dev) {
+  SSF_TRY(check_handle(h));
+  SSF_TRY(check_field(h, psi, "psi"));
+  if (!out_dev) return fail(SSF_E_INVALID, "out_dev is null");
+  const dim3 grid((unsigned)ceil_div(h->n[0], 256), (unsigned)h->n[2]);
+  if (h->dti == 0)
+    hipLaunchKernelGGL(density_xz_kernel<float2>, grid, dim3(256), 0, h->stream, (const float2*)psi, h->n[0], h->n[1],
+                       h->d[1], out_dev);
+  else
+    hipLaunchKernelGGL(density_xz_kernel<double2>, grid, dim3(256), 0, h->stream, (const double2*)psi, h->n[0],
+                       h->n[1], h->d[1], out_dev);
+  HIP_TRY(hipGetLastError());
+  return SSF_OK;
+}
+
 ssf_status ssf_sync(ssf_handle* h) {
   SSF_TRY(check_handle(h));
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1018,10 +1070,11 @@ ssf_status ssf_adjoint_init(ssf_handle* h, const void* psi, void* lambda) {
   const unsigned blocks = (unsigned)std::min<long long>(ceil_div(h->npts, 256), 65536);
   if (h->dti == 0)
     hipLaunchKernelGGL(mask_kernel<float2>, dim3(blocks), dim3(256), 0, h->stream, (const float2*)psi, (float2*)lambda,
-                       h->npts, h->n[0], h->ix_hi);
+                       h->npts, h->n[0], (long long)h->n[0] * h->n[1], h->ix_hi, h->zpart ? h->ixz : nullptr);
   else
     hipLaunchKernelGGL(mask_kernel<double2>, dim3(blocks), dim3(256), 0, h->stream, (const double2*)psi,
-                       (double2*)lambda, h->npts, h->n[0], h->ix_hi);
+                       (double2*)lambda, h->npts, h->n[0], (long long)h->n[0] * h->n[1], h->ix_hi,
+                       h->zpart ? h->ixz : nullptr);
   HIP_TRY(hipGetLastError());
   return SSF_OK;
 }

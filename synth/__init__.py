@@ -112,6 +112,14 @@ def ctap_profile(z, d0, delta, z1, z3, wg):
     return np.stack([x1, np.zeros_like(z), x3])
 
 
+def midlines(xc):
+    """Plane-dependent guide regions: the midlines between neighbouring guide
+    centres, x_lo(z) = (x1 + x2)/2 and x_hi(z) = (x2 + x3)/2 for xc of shape
+    (3, Nz)."""
+    xc = np.asarray(xc, dtype=np.float64)
+    return 0.5 * (xc[0] + xc[1]), 0.5 * (xc[1] + xc[2])
+
+
 def ctap_guides(grid: Grid, d0=3.0, delta=1.2, v0=40.0, sigma=0.6, z1=6.0, z3=-6.0, wg=8.0,
                 v0s=None, sigmas=None):
     z = grid.axis(2)
@@ -155,11 +163,12 @@ def config1():
     return dict(name="harmonic 64^3", grid=g, psi0=psi0, V=V, dt=0.005, steps=200)
 
 
-def config2(n=(256, 256, 512)):
+def config2(n=(256, 256, 512), intuitive=False):
     """Three-guide CTAP, 256 x 256 x 512 on [-8,8)^2 x [-64,64), 10^4 real steps
-    at dt = 0.002, z packet at z0 = -30 (width 4) moving with k_z = 3."""
+    at dt = 0.002, z packet at z0 = -30 (width 4) moving with k_z = 3.
+    intuitive=True swaps the bumps (the 1-2 pair approaches first)."""
     g = Grid(tuple(n), (-8.0, -8.0, -64.0), (8.0, 8.0, 64.0))
-    guides = ctap_guides(g)
+    guides = ctap_guides(g, z1=-6.0, z3=6.0) if intuitive else ctap_guides(g)
     return dict(name="ctap %dx%dx%d" % tuple(n), grid=g, guides=guides, dt=0.002,
                 steps=10000, imag_steps=2000, z0=-30.0, zwidth=4.0, kz=3.0)
 
