@@ -37,6 +37,10 @@ Further sections (each can be skipped with --sections):
            complex128.
   tvt      the headline workload in the T/2 - V - T/2 ordering (complex64,
            --tvt-steps steps): rate and distance from the V/2 - T - V/2 run.
+  obs      the headline workload with the guide regions bounded by the
+           midlines between the moving guides, in the counter-intuitive and
+           the intuitive bump order: populations against time, rate, and the
+           y-integrated x-z density of the final state (time per snapshot).
 """
 from __future__ import annotations
 
@@ -53,7 +57,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point split-step updates/s + HBM GB/s vs roofline, c64 vs c128 at ≤1e-4 L2"
-ALL_SECTIONS = ("c128", "cpu", "batch", "adjoint", "c3", "tvt")
+ALL_SECTIONS = ("c128", "cpu", "batch", "adjoint", "c3", "tvt", "obs")
 
 
 def log(*a):
@@ -380,6 +384,62 @@ def section_adjoint(torch, ssf, device, steps=None):
 
 
 # ---------------------------------------------------------------------------
+# time-resolved populations between the moving guides, x-z density
+# ---------------------------------------------------------------------------
+def section_obs(torch, ssf, device, n, steps, obs_every, imag_steps):
+    import numpy as np
+    import synth
+    out = {}
+    for label, intuitive in (("counter_intuitive", False), ("intuitive", True)):
+        cfg = synth.config2(n, intuitive=intuitive)
+        cfg["imag_steps"] = imag_steps if imag_steps is not None else cfg["imag_steps"]
+        g, gd = cfg["grid"], cfg["guides"]
+        log("obs: %s order, midline partitions, %d steps" % (label, steps))
+        psi0 = c2_initial_state(torch, ssf, cfg, device)
+        s = ssf.Solver(g.n, g.lo, g.hi, "c64", device=device)
+        s.set_guides(gd.v0, gd.sigma, gd.xc)
+        xl, xh = synth.midlines(gd.xc)
+        s.set_partition_z(xl, xh)
+        s.tune(reps=10)
+        psi = psi0.to(s.tdtype).contiguous()
+        obs = s.obs_buffer(steps // obs_every)
+        s.step(psi.clone(), 20, cfg["dt"])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(psi, steps, cfg["dt"], obs_every=obs_every, obs_buf=obs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rec = s.read_obs(obs, steps // obs_every)
+        stride = max(1, len(rec) // 20)
+        out[label] = {"value": g.points * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                      "t": [float(r["step"]) * cfg["dt"] for r in rec[::stride]],
+                      "pops": [[float(v) for v in r["pop"]] for r in rec[::stride]],
+                      "final_pops": [float(v) for v in rec[-1]["pop"]]}
+        # y-integrated density of the final state (Fig. 5 analog)
+        rho = s.density_xz(psi)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(20):
+            s.density_xz(psi, rho)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        r = rho.cpu().numpy()
+        x = g.axis(0)
+        out[label]["density_us"] = us
+        out[label]["density_gbs"] = (8.0 * g.points + 8.0 * g.n[0] * g.n[2]) / us / 1e3
+        out[label]["density_mean_x"] = float(np.sum(r * x[None, :]) / np.sum(r))
+        out[label]["density_total"] = float(np.sum(r) * g.spacing(0) * g.spacing(2))
+        s.close()
+        del psi, psi0
+        torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # 512^3
 # ---------------------------------------------------------------------------
 def section_c3(torch, ssf, device, steps=None, obs_every=100):
@@ -433,6 +493,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=None)
     ap.add_argument("--c3-steps", type=int, default=None)
     ap.add_argument("--tvt-steps", type=int, default=1000)
+    ap.add_argument("--obs-steps", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the library's plain field copy (2 x field bytes per launch), which "
                          "calibrates profiler byte counters")
@@ -547,6 +608,8 @@ def main():
                       "norm_drift": float(rt["rec"][-1]["norm"] - 1.0) if rt["rec"] is not None else None}
         del rt, rv
         torch.cuda.empty_cache()
+    if "obs" in sections:
+        out["obs"] = section_obs(torch, ssf, device, n, a.obs_steps, a.obs_every, a.imag_steps)
     if "batch" in sections:
         out["batch"] = section_batch(torch, ssf, device, steps=a.batch_steps)
         torch.cuda.empty_cache()

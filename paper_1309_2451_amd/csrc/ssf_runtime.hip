@@ -281,6 +281,7 @@ __global__ void __launch_bounds__(256) density_xz_kernel(const S* in, int nx, in
   if (x >= nx) return;
   const S* p = in + (long long)z * ny * nx + x;
   double s = 0.0;
+#pragma unroll 8
   for (int y = 0; y < ny; ++y) {
     const double2 v = ssf::ld2(p + (long long)y * nx);
     s += v.x * v.x + v.y * v.y;
