@@ -94,7 +94,7 @@ template <int N> struct Shape {
     while (px > 1 && px * N > LDS_CAP_ELEMS) px /= 2;
     return px;
   }
-  static constexpr int so(int dt, int var = 0) {   // strided tile depth (outer pencils)
+  static constexpr int so(int dt, int /*var*/ = 0) {   // strided tile depth (outer pencils), both variants
     int po = 256 * E / (N * sx0(dt));
     if (po < 1) po = 1;
     while (po > 1 && sx0(dt) * po * N > LDS_CAP_ELEMS) po /= 2;
@@ -114,7 +114,7 @@ template <int N> struct Shape {
   // the workgroup and half the LDS, so twice as many workgroups share a CU
   static constexpr bool v1(int dt) { return sx0(dt) > 1; }
   static constexpr int sx(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sx0(dt) / 2 : sx0(dt); }
-  static constexpr int sm(int dt, int var = 0) { return sm0(dt); }
+  static constexpr int sm(int dt, int /*var*/ = 0) { return sm0(dt); }
   static constexpr int ldrow() { return N; }
   static constexpr int cr() {              // contiguous rows per workgroup
     int rows = 256 * E / N;
@@ -632,7 +632,7 @@ __device__ __forceinline__ unsigned elem_off(unsigned off, int n, const PassArgs
 // Tables: read from global memory.
 template <class G, int r>
 __device__ __forceinline__ void potentials(const PassArgs& a, const double* sA, const double* sB,
-                                           const Pen<G, r>& p, int z, double (&V)[G::E]) {
+                                           const Pen<G, r>& p, double (&V)[G::E]) {
   constexpr int N = G::NN, U = Pen<G, r>::U;
   if (a.vkind == V_CTAP) {
 #pragma unroll
@@ -843,7 +843,7 @@ pass_kernel(PassArgs a) {
         }
         if (a.pre & PRE_VPHASE) {
           double V[E];
-          potentials<G, r0>(a, s_A, s_dyn, p, t1, V);
+          potentials<G, r0>(a, s_A, s_dyn, p, V);
 #pragma unroll
           for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpre, a.imag));
         }
@@ -882,7 +882,7 @@ pass_kernel(PassArgs a) {
               for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt<LOWP>(V[e] * a.cmid));
             }
           } else {
-            potentials<G, rm>(a, s_A, s_dyn, p, t1, V);
+            potentials<G, rm>(a, s_A, s_dyn, p, V);
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cmid, a.imag));
           }
@@ -909,7 +909,7 @@ pass_kernel(PassArgs a) {
       if constexpr (LEAN) {
       } else if constexpr (CONTIG) {
         double V[E];
-        if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, p, t1, V);
+        if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, p, V);
         if (a.post & POST_VPHASE) {
 #pragma unroll
           for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpost, a.imag));
