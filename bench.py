@@ -18,8 +18,11 @@ Per-pass kernel times come from HIP events that the library records around
 each pass launch on its own stream during the timed region; the dominant
 pass gives the roofline entry.  HBM traffic of that kernel comes from the
 profiler byte counters kept under profiles/ (used only if they were taken
-on the current kernel sources).  The CPU baseline is the FP64 oracle on a
-bounded sample of the same workload.
+on the current kernel sources).  The library's plain copy of one field,
+timed the same way, gives the bandwidth a pass that only streams the field
+reaches on this device; the step and the dominant pass are also stated as
+fractions of it.  The CPU baseline is the FP64 oracle on a bounded sample of
+the same workload.
 
 Further sections (each can be skipped with --sections):
   batch    96 instances of uneven grids (seeded), complex64, 2000 steps at
@@ -495,8 +498,8 @@ def main():
     ap.add_argument("--tvt-steps", type=int, default=1000)
     ap.add_argument("--obs-steps", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run the library's plain field copy (2 x field bytes per launch), which "
-                         "calibrates profiler byte counters")
+                    help="record the plain field copy launches (2 x field bytes each) for calibrating "
+                         "profiler byte counters")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path (got --gpus %d)" % a.gpus,
@@ -584,17 +587,31 @@ def main():
         out["c64_vs_c128_rel_l2"] = rel_l2(torch, r64["psi"], r128["psi"])
         out["c64_vs_c128_steps"] = a.steps
         del r128
+    # the library's plain copy of one complex64 field: the bandwidth a pass
+    # that only streams the field in and out reaches on this device (timed on
+    # the solver's stream, torch's current stream)
+    log("plain copy of one complex64 field, 3 + 10 launches")
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64", device=device)
+    src = r64["psi"]
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        s.copy(src, dst)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        s.copy(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    s.close()
+    copy_bytes = 2 * src.numel() * src.element_size()
+    copy_gbs = copy_bytes / (e0.elapsed_time(e1) * 1e-3 / 10) / 1e9
+    out["copy"] = {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS, "bytes_per_launch": copy_bytes,
+                   "step_algorithmic_frac_of_copy": step_gbs / copy_gbs,
+                   "roofline_kernel_frac_of_copy": achieved / copy_gbs}
     if a.calibrate_copy:
-        log("plain copy of one complex64 field, 3 launches")
-        s = ssf.Solver(g.n, g.lo, g.hi, "c64", device=device)
-        src = r64["psi"]
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            s.copy(src, dst)
-        torch.cuda.synchronize()
-        s.close()
-        out["copy_calibration"] = {"bytes_per_launch": 2 * src.numel() * src.element_size(), "launches": 3}
-        del dst
+        out["copy_calibration"] = {"bytes_per_launch": copy_bytes, "launches": 13}
+    del dst
     del r64
     torch.cuda.empty_cache()
 
