@@ -36,8 +36,8 @@ Further sections (each can be skipped with --sections):
            time and device memory per gradient, complex64 vs complex128,
            against the cost of central differences with the plain path.
   c3       512^3, seeded +-5 % guide parameters, 500 imaginary-time steps on
-           the full grid, then 5000 real-time steps in complex64 and
-           complex128.
+           the full grid (complex128, timed: imag_c128), then 5000 real-time
+           steps in complex64 and complex128.
   tvt      the headline workload in the T/2 - V - T/2 ordering (complex64,
            --tvt-steps steps): rate and distance from the V/2 - T - V/2 run.
   obs      the headline workload with the guide regions bounded by the
@@ -457,12 +457,23 @@ def section_c3(torch, ssf, device, steps=None, obs_every=100):
     del phi
     s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
     s.set_guides(gd.v0, gd.sigma, gd.xc)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
     s.step(psi, cfg["imag_steps"], cfg["dt"], imag=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_imag = e0.elapsed_time(e1)
     s.close()
     z = torch.tensor(g.axis(2), dtype=torch.float64, device=device)
     psi.mul_(torch.exp(1j * cfg["kz"] * z)[:, None, None])
     out = {"workload": "512^3 guide transfer, v0 and sigma +-5%% (seed 3), %d imaginary + %d real steps, dt=%g"
-                       % (cfg["imag_steps"], steps, cfg["dt"])}
+                       % (cfg["imag_steps"], steps, cfg["dt"]),
+           # imaginary time (complex128, renormalised every step from the fused FP64 norm),
+           # timed on torch's current stream, which the solver uses
+           "imag_c128": {"steps": cfg["imag_steps"], "ms_per_step": ms_imag / cfg["imag_steps"],
+                         "value": g.points * cfg["imag_steps"] / (ms_imag * 1e-3)}}
     runs = {}
     for dtype in ("c64", "c128"):
         log("c3: %s, %d steps" % (dtype, steps))
