@@ -9,7 +9,9 @@ namespace ssf {
 // Operation codes applied on the way in (pre), between the two transforms of
 // a fused pass (mid), and on the way out (post).
 enum : int { PRE_SCALE = 1, PRE_VPHASE = 2, PRE_ADJ = 4 };
-enum : int { MID_NONE = 0, MID_KINETIC = 1, MID_VPHASE = 2 };
+// MID_VNORM: two potential half-steps with the field's norm summed between
+// them (imaginary time: the end of one step and the start of the next).
+enum : int { MID_NONE = 0, MID_KINETIC = 1, MID_VPHASE = 2, MID_VNORM = 3 };
 enum : int { POST_VPHASE = 1, POST_OBS = 2, POST_ADJ = 4, POST_KIN = 8 };
 // Potential sources.
 enum : int { V_NONE = 0, V_TAB64 = 1, V_TAB32 = 2, V_CTAP = 3 };

@@ -864,7 +864,7 @@ pass_kernel(PassArgs a) {
     if constexpr (FUSED) {
       // outputs of the last stage sit at n = i + q N / rm
       if constexpr (CONTIG) {
-        if (a.mid == MID_VPHASE) {
+        if (a.mid == MID_VPHASE || (!LEAN && a.mid == MID_VNORM)) {
           Pen<G, rm> p;
           pencils(p, a, t);
           double V[E];
@@ -889,6 +889,22 @@ pass_kernel(PassArgs a) {
             } else {
 #pragma unroll
               for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt<LOWP>(V[e] * a.cmid));
+            }
+          } else if (a.mid == MID_VNORM) {
+            // end of one step (half-step factor), the norm of that step's
+            // field (FP64, ragged rows weighted zero), start of the next
+            potentials<G, rm>(a, s_A, s_dyn, p, V);
+#pragma unroll
+            for (int u = 0; u < UM; ++u) {
+              const double w = p.ok[u] ? 1.0 : 0.0;
+#pragma unroll
+              for (int q = 0; q < rm; ++q) {
+                const int e = u * rm + q;
+                const double2 f = phase_factor<LOWP>(V[e] * a.cmid, a.imag);
+                v[e] = cmul(v[e], f);
+                acc[0] += w * (v[e].x * v[e].x + v[e].y * v[e].y);
+                v[e] = cmul(v[e], f);
+              }
             }
           } else {
             potentials<G, rm>(a, s_A, s_dyn, p, V);
@@ -981,7 +997,7 @@ pass_kernel(PassArgs a) {
     }
 
     if constexpr (!LEAN) {
-      if ((a.post & (POST_OBS | POST_ADJ | POST_KIN)) || (a.pre & PRE_ADJ))
+      if ((a.post & (POST_OBS | POST_ADJ | POST_KIN)) || (a.pre & PRE_ADJ) || (CONTIG && a.mid == MID_VNORM))
         block_sum<WG, NRED_OBS>(acc, a.partials + (long long)tg * NRED_OBS, red);
     }
   }

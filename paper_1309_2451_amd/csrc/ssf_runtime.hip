@@ -868,7 +868,13 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
     SSF_TRY(reduce_field(h, src));
     SSF_TRY(finalize_obs(h, nullptr, 0, 2, dt, nullptr, 0));
   }
-  const bool fuse = allow_fuse && h->fuse && !imag;
+  // Imaginary time renormalises after every step.  Unfused, each step ends
+  // with the x inverse pass summing the norm and the next x forward pass
+  // applies 1/norm^(1/2) on load.  Fused, the x pass between two steps sums
+  // the norm between its two potential half-steps (MID_VNORM) and the scale
+  // goes onto the input of the next x pass (every operation in between is
+  // linear), so a step costs the same four passes as in real time.
+  const bool fuse = allow_fuse && h->fuse;
   int64_t s = 0;
   const void* cur_in = src;
   while (s < nsteps) {
@@ -879,6 +885,7 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
     ax.imag = imag;
     SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
     cur_in = psi;
+    bool scaled = true;            // imaginary time: the field in flight carries the latest scale
     for (;;) {
       SSF_TRY(step_middle(h, psi, kt));
       ++s;
@@ -886,6 +893,7 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
       const bool end = !fuse || s == nsteps || obs_due;
       if (end) {
         PassArgs ai = base_args(h, psi, psi, 0);
+        ai.pre = (imag && !scaled) ? ssf::PRE_SCALE : 0;
         ai.post = ssf::POST_VPHASE | ((obs_due || imag) ? ssf::POST_OBS : 0);
         ai.cpost = 0.5 * dt;
         ai.imag = imag;
@@ -897,12 +905,21 @@ static ssf_status run_steps(ssf_handle* h, const void* src, void* psi, int64_t n
         break;
       }
       PassArgs am = base_args(h, psi, psi, 0);
-      am.mid = ssf::MID_VPHASE;
-      am.cmid = dt;
       am.imag = imag;
-      // |V dt| <= pi/4 lets the phase skip its argument reduction
-      am.small_phase = phase_tier(h->vkind, h->vmax, dt);
-      SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
+      if (imag) {
+        am.mid = ssf::MID_VNORM;
+        am.cmid = 0.5 * dt;
+        am.pre = scaled ? 0 : ssf::PRE_SCALE;
+        SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
+        SSF_TRY(finalize_obs(h, nullptr, s, 2, dt, nullptr, 0));
+        scaled = false;
+      } else {
+        am.mid = ssf::MID_VPHASE;
+        am.cmid = dt;
+        // |V dt| <= pi/4 lets the phase skip its argument reduction
+        am.small_phase = phase_tier(h->vkind, h->vmax, dt);
+        SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
+      }
     }
   }
   if (imag && nsteps > 0) SSF_TRY(scale_field(h, psi));

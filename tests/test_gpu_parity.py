@@ -172,6 +172,40 @@ def test_imaginary_time_vs_oracle(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("obs_every", [0, 7])
+def test_imaginary_time_fused_chain_vs_oracle(dtype, obs_every):
+    """Imaginary time with the step chain fused across observations: the norm
+    of every step is summed inside the x pass between two steps and the scale
+    rides on the next pass.  Final field against the oracle, step energies at
+    the observed steps against the oracle's, and the unfused path."""
+    say("imag fused", dtype, obs_every)
+    g = synth.Grid((32, 24, 40), (-6.0, -5.0, -7.0), (6.0, 5.0, 7.0))
+    V = synth.harmonic_table(g, (1.0, 1.3, 0.8))
+    psi0 = synth.gaussian_packet(g, centre=(0.3, -0.2, 0.5), width=(1.3, 0.7, 1.1))
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    dtau, n = 0.01, 30
+    ref, ed = oracle.step(psi0, V, g.lo, g.hi, dtau, n, imag=True)
+    out = {}
+    for fuse in (True, False):
+        s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+        s.set_potential_table(torch.from_numpy(V).to(DEV))
+        s.set_fusion(fuse)
+        t = to_dev(psi0, s)
+        obs = s.step(t, n, dtau, imag=True, obs_every=obs_every)
+        out[fuse] = host(t)
+        tol = 1e-12 if dtype == "c128" else 3 * 6e-8 * np.sqrt(5 * n)
+        assert rel(out[fuse], ref) < tol, fuse
+        if obs_every:
+            k = np.arange(obs_every, n + 1, obs_every)
+            assert np.max(np.abs(obs["energy"] - ed[k - 1])) < (1e-9 if dtype == "c128" else 1e-3)
+        o = s.observables(t)
+        assert abs(o["norm"] - 1.0) < (1e-13 if dtype == "c128" else 1e-6)
+        s.close()
+    assert rel(out[True], out[False]) < (1e-13 if dtype == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_observables_energy_vs_oracle(dtype):
     say("observables", dtype)
     g = synth.Grid((40, 24, 32), (-6.0, -5.0, -7.0), (6.0, 5.0, 7.0))
