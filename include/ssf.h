@@ -127,8 +127,10 @@ ssf_status ssf_set_partition(ssf_handle* h, double x_lo, double x_hi);
 ssf_status ssf_set_partition_z(ssf_handle* h, const double* x_lo, const double* x_hi);
 /* 0: one Strang step = 5 passes; 1 (default): consecutive steps without an
  * observation between them share one x pass (exp(-i V dt) between the inverse
- * and the next forward x transform), 4 passes per step.  Same result up to
- * rounding. */
+ * and the next forward x transform), 4 passes per step.  In imaginary time
+ * that shared x pass also sums the norm of the field between its two
+ * potential half-steps, and the renormalisation rides on the next pass's
+ * input.  Same result up to rounding. */
 ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
 /* Ordering of the symmetric split step taken by ssf_step in real time:
  * SSF_SPLIT_VTV (default) = exp(-iV dt/2) exp(-iT dt) exp(-iV dt/2);
