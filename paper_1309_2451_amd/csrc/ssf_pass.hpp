@@ -711,10 +711,11 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 
 // passes: workgroup w takes tiles w, w + gridDim.x, ..., so the workgroups
 // in flight together cover whole rows of consecutive outer pencils (one
 // contiguous stretch of memory per plane) instead of one 128-byte segment
-// each from rows far apart (measured faster for both).  Twiddles, the z kinetic table and (x passes) the guide
-// tables live in LDS, so while a tile is transformed the only vector-memory
-// reads in flight are the prefetch of the next tile's values (and of its
-// per-pencil kinetic factors), which therefore overlap the arithmetic.
+// each from rows far apart (measured faster for both).  Twiddles, the z
+// kinetic table and (x passes) the guide tables live in LDS, so while a tile
+// is transformed the only vector-memory reads in flight are the prefetch of
+// the next tile's values (and of its per-pencil kinetic factors), which
+// therefore overlap the arithmetic.
 template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH>
 __global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM))
 pass_kernel(PassArgs a) {
