@@ -60,7 +60,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point split-step updates/s + HBM GB/s vs roofline, c64 vs c128 at ≤1e-4 L2"
-ALL_SECTIONS = ("c128", "cpu", "batch", "adjoint", "c3", "tvt", "obs")
+ALL_SECTIONS = ("c128", "accuracy", "cpu", "batch", "adjoint", "c3", "tvt", "obs")
+ACCURACY_STEPS = 10000
 
 
 def log(*a):
@@ -73,25 +74,14 @@ def log(*a):
 def transverse_ground_state(torch, ssf, g, v0, sigma, xc, steps, dtau, device):
     """(1, Ny, Nx) complex128: imaginary-time ground state of one guide
     (depth v0, width sigma, centre x = xc) on the transverse plane of g."""
-    import numpy as np
-    s2 = ssf.Solver((g.n[0], g.n[1], 1), (g.lo[0], g.lo[1], 0.0), (g.hi[0], g.hi[1], 1.0), "c128", device=device)
-    s2.set_guides([v0], [sigma], np.array([[xc]], dtype=np.float64))
-    x = torch.tensor(g.axis(0), dtype=torch.float64, device=device)
-    y = torch.tensor(g.axis(1), dtype=torch.float64, device=device)
-    phi = torch.exp(-((x[None, :] - xc) ** 2 + y[:, None] ** 2) / (2 * sigma ** 2)).to(torch.complex128)
-    phi = phi.reshape(1, g.n[1], g.n[0]).contiguous()
-    s2.step(phi, steps, dtau, imag=True)
-    s2.close()
-    return phi
+    from paper_1309_2451_amd.states import transverse_ground_state as tgs
+    return tgs(torch, g.n[:2], g.lo[:2], g.hi[:2], v0, sigma, xc, steps, dtau, device)
 
 
 def packet(torch, g, phi, z0, zwidth, kz, device):
     """phi(x, y) * exp(-(z - z0)^2 / (2 w^2) + i kz z), normalised on the grid (complex128)."""
-    z = torch.tensor(g.axis(2), dtype=torch.float64, device=device)
-    fz = torch.exp(-((z - z0) ** 2) / (2 * zwidth ** 2)).to(torch.complex128) * torch.exp(1j * kz * z)
-    psi = (fz[:, None, None] * phi).contiguous()
-    nrm = torch.sqrt(torch.sum(torch.abs(psi) ** 2) * g.dv)
-    return (psi / nrm).contiguous()
+    from paper_1309_2451_amd.states import packet as pk
+    return pk(torch, g, phi, z0, zwidth, kz, device)
 
 
 def guide_index(g, z0):
@@ -99,27 +89,41 @@ def guide_index(g, z0):
 
 
 def c2_initial_state(torch, ssf, cfg, device):
-    g, gd = cfg["grid"], cfg["guides"]
-    xc = float(gd.xc[0, guide_index(g, cfg["z0"])])
-    phi = transverse_ground_state(torch, ssf, g, gd.v0[0], gd.sigma[0], xc, cfg["imag_steps"], cfg["dt"], device)
-    return packet(torch, g, phi, cfg["z0"], cfg["zwidth"], cfg["kz"], device)
+    from paper_1309_2451_amd.states import guide_transfer_state
+    return guide_transfer_state(torch, cfg, device)
 
 
 # ---------------------------------------------------------------------------
 # one timed run of a single field
 # ---------------------------------------------------------------------------
 def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tune=True, timing=True,
-              splitting="vtv"):
+              splitting="vtv", tiles=None, window=0):
+    """One storage type on the workload: tile choice (autotuner unless `tiles`
+    is given), then `window` steps with per-pass HIP events on a scratch copy
+    (the steady-state pass times of the roofline entry), `warmup` untimed
+    steps, and exactly `steps` timed steps (per-pass events only if `timing`)."""
     g, gd = cfg["grid"], cfg["guides"]
     s = ssf.Solver(g.n, g.lo, g.hi, dtype, device=device)
     s.set_splitting(splitting)
     s.set_guides(gd.v0, gd.sigma, gd.xc)
     s.set_partition(gd.x_lo, gd.x_hi)
     tune_info = None
-    if tune:
-        tiles, tune_us = s.tune(reps=10)          # tile autotuner (outside the timed region)
-        tune_info = {"choice": tiles, "us": {"axis%d_variant%d" % k: v for k, v in tune_us.items()}}
-    obs = s.obs_buffer(max(1, max(steps, warmup) // obs_every))
+    if tiles is not None:
+        s.set_tiles(tiles)
+        tune_info = {"choice": list(tiles), "us": None}
+    elif tune:
+        ch, tune_us = s.tune(reps=10)             # tile autotuner (outside the timed region)
+        tune_info = {"choice": ch, "us": {"axis%d_variant%d" % k: v for k, v in tune_us.items()}}
+    obs = s.obs_buffer(max(1, max(steps, warmup, window) // obs_every))
+    win = None
+    if window:
+        scratch = psi0.to(s.tdtype).contiguous().clone()
+        torch.cuda.synchronize()
+        s.set_timing(True)
+        s.step(scratch, window, cfg["dt"], obs_every=obs_every, obs_buf=obs)
+        win = s.timing_read()
+        s.set_timing(False)
+        del scratch
     if warmup:
         scratch = psi0.to(s.tdtype).contiguous().clone()
         s.step(scratch, warmup, cfg["dt"], obs_every=obs_every, obs_buf=obs)
@@ -141,7 +145,7 @@ def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tu
     nobs = steps // obs_every
     rec = s.read_obs(obs, nobs) if nobs else None
     s.close()
-    return dict(psi=psi, ms=ms, passes=passes, rec=rec, tune=tune_info)
+    return dict(psi=psi, ms=ms, passes=passes, rec=rec, tune=tune_info, window=win)
 
 
 def pass_summary(passes):
@@ -186,6 +190,23 @@ def measured_traffic(kernel_kind, variant, grid_n, dtype):
 PASS_AXIS = {"x_fwd": 0, "x_inv": 0, "x_inv_phase_fwd": 0, "yz_fwd": 1, "yz_inv": 1, "z_fwd_kin_inv": 2}
 
 
+def roofline_entry(passes, grid, esize, tiles, storage):
+    """Roofline of the pass kind with the largest total time in `passes`
+    ({kind: (ms, launches)}, HIP events around every launch): algorithmic
+    bytes per launch (one read and one write of the field) over the average
+    launch duration, against the 8 TB/s HBM peak."""
+    name, (tot_ms, n) = max(passes.items(), key=lambda kv: kv[1][0])
+    avg_s = tot_ms * 1e-3 / max(n, 1)
+    bpl = 2.0 * esize * grid.points
+    achieved = bpl / avg_s / 1e9
+    var = tiles[PASS_AXIS[name]] if tiles else 0
+    traffic = measured_traffic(name, var, grid.n, storage)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name, "tile_variant": var,
+            "kernel_avg_us": avg_s * 1e6, "launches": n, "bytes_per_launch": bpl,
+            "gap_to_0.6": 0.6 - achieved / HBM_PEAK_GBS}
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample
 # ---------------------------------------------------------------------------
@@ -205,11 +226,32 @@ def cpu_baseline(cfg, target_s=15.0):
     t0 = time.perf_counter()
     oracle.step(psi, V, g.lo, g.hi, cfg["dt"], n)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cores = min(cores, os.cpu_count() or cores)
-    return {"value": g.points * n / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
+    threads = oracle.threads()
+    # one thread: one whole-grid step (the same work, about 16 x longer)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(psi, V, g.lo, g.hi, cfg["dt"], 1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    return {"value": g.points * n / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": "%d Strang steps of the full %dx%dx%d grid with the guide potential (FP64, OpenMP over "
-                      "pencils), %.1f s" % (n, g.n[0], g.n[1], g.n[2], dt)}
+                      "pencils on %d threads), %.1f s" % (n, g.n[0], g.n[1], g.n[2], threads, dt),
+            "single_thread": {"value": g.points / dt1, "unit": "updates/s", "cores": 1,
+                              "sample": "1 Strang step of the full grid, %.1f s" % dt1},
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 # ---------------------------------------------------------------------------
@@ -377,8 +419,10 @@ def section_adjoint(torch, ssf, device, steps=None):
     nparam = 2 * cfg["M"]
     g64, g128 = grads["c64"], grads["c128"]
     out["plain_c128_forward_s"] = fwd128
-    out["central_fd_c128_s"] = 2 * nparam * fwd128
-    out["speedup_c64_adjoint_vs_fd_c128"] = 2 * nparam * fwd128 / out["c64"]["gradient_s"]
+    # not run: 2 x (number of coefficients) measured plain forward runs
+    out["central_fd_c128_s_estimate"] = 2 * nparam * fwd128
+    out["central_fd_c128_estimate_basis"] = "2 x %d x plain_c128_forward_s (not run)" % nparam
+    out["speedup_c64_adjoint_vs_fd_c128_estimate"] = 2 * nparam * fwd128 / out["c64"]["gradient_s"]
     out["speedup_c64_adjoint_vs_c128_adjoint"] = out["c128"]["gradient_s"] / out["c64"]["gradient_s"]
     out["grad_rel_err_c64_vs_c128"] = float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128))
     out["F_abs_err_c64_vs_c128"] = abs(out["c64"]["F"] - out["c128"]["F"])
@@ -485,6 +529,9 @@ def section_c3(torch, ssf, device, steps=None, obs_every=100):
                       "step_algorithmic_gbs": launches * 2.0 * esize * g.points / (r["ms"] * 1e-3) / 1e9,
                       "final_p3": float(r["rec"][-1]["pop"][2]), "norm_drift": float(r["rec"][-1]["norm"] - 1.0),
                       "tiles": r["tune"]}
+        out[dtype]["step_algorithmic_frac"] = out[dtype]["step_algorithmic_gbs"] * 1e9 / (HBM_PEAK_GBS * 1e9)
+        out[dtype]["roofline"] = roofline_entry(r["passes"], g, esize, r["tune"]["choice"] if r["tune"] else None,
+                                                dtype)
         runs[dtype] = r["psi"]
     out["c64_vs_c128_rel_l2"] = rel_l2(torch, runs["c64"], runs["c128"])
     out["c64_speedup_vs_c128"] = out["c64"]["value"] / out["c128"]["value"]
@@ -497,6 +544,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--obs-every", type=int, default=100)
+    ap.add_argument("--roofline-steps", type=int, default=520,
+                    help="steps of the steady window whose per-pass HIP events give the roofline entry "
+                         "(520 steps: at least 500 launches of every pass kind of the step)")
     ap.add_argument("--grid", type=str, default="256,256,512", help="Nx,Ny,Nz of the headline workload")
     ap.add_argument("--sections", type=str, default=",".join(ALL_SECTIONS),
                     help="comma list of extra sections to run: " + ",".join(ALL_SECTIONS) + " (none: headline only)")
@@ -535,21 +585,24 @@ def main():
     log("initial state on %s" % (g.n,))
     psi0 = c2_initial_state(torch, ssf, cfg, device)
 
-    log("c64 run, %d warmup + %d timed steps" % (a.warmup, a.steps))
-    r64 = timed_run(torch, ssf, cfg, psi0, "c64", a.steps, a.warmup, a.obs_every, device)
+    log("c64 run: tile autotuner, %d-step steady window, %d warmup + %d timed steps"
+        % (a.roofline_steps, a.warmup, a.steps))
+    r64 = timed_run(torch, ssf, cfg, psi0, "c64", a.steps, a.warmup, a.obs_every, device, timing=False,
+                    window=a.roofline_steps)
     ms64 = r64["ms"]
     ups64 = g.points * a.steps / (ms64 * 1e-3)
+    tiles = r64["tune"]["choice"]
 
-    # roofline entry: the pass kind with the largest total time in the timed region
+    # passes in the timed region: every chain of the fused step sequence is
+    # x forward, (y, z, y) per step, a fused x pass between its steps and an x
+    # inverse; chains end at observations and at the last step
     esize = 8
-    dom_name, (dom_ms, dom_n) = max(r64["passes"].items(), key=lambda kv: kv[1][0])
-    avg_s = dom_ms * 1e-3 / max(dom_n, 1)
-    bytes_per_launch = 2.0 * esize * g.points            # read + write psi once
-    achieved = bytes_per_launch / avg_s / 1e9
-    dom_var = r64["tune"]["choice"][PASS_AXIS[dom_name]] if r64["tune"] else 0
-    traffic = measured_traffic(dom_name, dom_var, g.n, "c64")
-    launches = sum(c for _, c in r64["passes"].values())
+    chains = a.steps // a.obs_every + (1 if a.steps % a.obs_every else 0)
+    launches = 4 * a.steps + chains
     step_gbs = launches * 2.0 * esize * g.points / (ms64 * 1e-3) / 1e9
+    # roofline entry: the dominant pass of the steady window (HIP events around every launch)
+    roof = roofline_entry(r64["window"], g, esize, tiles, "c64")
+    roof["window_steps"] = a.roofline_steps
 
     out = {
         "metric": METRIC,
@@ -567,13 +620,12 @@ def main():
         "config": {"workload": "three-guide transfer %dx%dx%d, complex64 storage, FP64 arithmetic, dt=0.002, "
                                "observables every %d steps" % (g.n[0], g.n[1], g.n[2], a.obs_every),
                    "grid": list(g.n), "storage": "complex64", "arithmetic": "f64", "obs_every": a.obs_every},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name, "tile_variant": dom_var,
-                     "kernel_avg_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch},
+        "roofline": roof,
         "step_algorithmic_gbs": step_gbs,
         "step_algorithmic_frac": step_gbs / HBM_PEAK_GBS,
         "passes_per_step": launches / a.steps,
-        "pass_times": pass_summary(r64["passes"]),
+        "pass_times": pass_summary(r64["window"]),
+        "pass_times_window_steps": a.roofline_steps,
         "tiles": r64["tune"],
     }
     if r64["rec"] is not None and len(r64["rec"]):
@@ -582,13 +634,12 @@ def main():
 
     if "c128" in sections:
         log("c128 run")
-        r128 = timed_run(torch, ssf, cfg, psi0, "c128", a.steps, a.warmup, a.obs_every, device)
+        r128 = timed_run(torch, ssf, cfg, psi0, "c128", a.steps, a.warmup, a.obs_every, device, timing=False,
+                         window=a.roofline_steps)
         ups128 = g.points * a.steps / (r128["ms"] * 1e-3)
-        d128, (m128, n128) = max(r128["passes"].items(), key=lambda kv: kv[1][0])
-        avg128 = m128 * 1e-3 / max(n128, 1)
-        out["c128"] = {"value": ups128, "ms_per_step": r128["ms"] / a.steps, "kernel": d128,
-                       "kernel_avg_us": avg128 * 1e6, "achieved_gbs": 2.0 * 16 * g.points / avg128 / 1e9,
-                       "pass_times": pass_summary(r128["passes"]), "tiles": r128["tune"]}
+        out["c128"] = {"value": ups128, "ms_per_step": r128["ms"] / a.steps,
+                       "roofline": roofline_entry(r128["window"], g, 16, r128["tune"]["choice"], "c128"),
+                       "pass_times": pass_summary(r128["window"]), "tiles": r128["tune"]}
         if r128["rec"] is not None and len(r128["rec"]):
             out["c128"]["final_populations"] = [float(v) for v in r128["rec"][-1]["pop"]]
             out["c128"]["norm_drift"] = float(r128["rec"][-1]["norm"] - 1.0)
@@ -598,6 +649,31 @@ def main():
         out["c64_vs_c128_rel_l2"] = rel_l2(torch, r64["psi"], r128["psi"])
         out["c64_vs_c128_steps"] = a.steps
         del r128
+    if "accuracy" in sections:
+        # the accuracy targets are stated after 10^4 steps, whatever --steps is
+        n_acc = ACCURACY_STEPS
+        log("accuracy: %d steps in complex64 and complex128 from the same state" % n_acc)
+        runs = {}
+        for dtype in ("c64", "c128"):
+            if dtype == "c64" and a.steps == n_acc:
+                runs[dtype] = r64
+            else:
+                runs[dtype] = timed_run(torch, ssf, cfg, psi0, dtype, n_acc, 0, a.obs_every, device, timing=False,
+                                        tiles=tiles if dtype == "c64" else None)
+        q64, q128 = runs["c64"], runs["c128"]
+        l2 = rel_l2(torch, q64["psi"], q128["psi"])
+        d64 = float(q64["rec"][-1]["norm"] - 1.0)
+        d128 = float(q128["rec"][-1]["norm"] - 1.0)
+        p64, p128 = float(q64["rec"][-1]["pop"][2]), float(q128["rec"][-1]["pop"][2])
+        out["accuracy_1e4"] = {
+            "steps": n_acc, "rel_l2_c64_vs_c128": l2, "c64_norm_drift": d64, "c128_norm_drift": d128,
+            "p3_c64": p64, "p3_c128": p128, "p3_abs_err": abs(p64 - p128),
+            "c64_ms_per_step": q64["ms"] / n_acc, "c128_ms_per_step": q128["ms"] / n_acc,
+            "c64_speedup_vs_c128": q128["ms"] / q64["ms"],
+            "targets": {"rel_l2": 1e-4, "abs_norm_drift": 1e-5},
+            "met": bool(l2 <= 1e-4 and abs(d64) <= 1e-5)}
+        del runs, q64, q128
+        torch.cuda.empty_cache()
     # the library's plain copy of one complex64 field: the bandwidth a pass
     # that only streams the field in and out reaches on this device (timed on
     # the solver's stream, torch's current stream)
@@ -619,7 +695,7 @@ def main():
     copy_gbs = copy_bytes / (e0.elapsed_time(e1) * 1e-3 / 10) / 1e9
     out["copy"] = {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS, "bytes_per_launch": copy_bytes,
                    "step_algorithmic_frac_of_copy": step_gbs / copy_gbs,
-                   "roofline_kernel_frac_of_copy": achieved / copy_gbs}
+                   "roofline_kernel_frac_of_copy": roof["achieved"] / copy_gbs}
     if a.calibrate_copy:
         out["copy_calibration"] = {"bytes_per_launch": copy_bytes, "launches": 13}
     del dst

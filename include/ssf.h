@@ -246,6 +246,9 @@ ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf
 ssf_status ssf_batch_run(ssf_batch* b, void* const* psi, int64_t nsteps, double dt, int64_t chunk,
                          ssf_obs* obs_dev);
 ssf_status ssf_batch_tune(ssf_batch* b, int32_t reps);
+/* Order later runs after the work enqueued on `hip_stream` (and work enqueued
+ * there afterwards after them), in place of the stream given at creation. */
+ssf_status ssf_batch_set_stream(ssf_batch* b, void* hip_stream);
 /* Number of groups and the group of each instance (group_of[count], may be NULL). */
 ssf_status ssf_batch_info(ssf_batch* b, int32_t* ngroups, int32_t* group_of);
 ssf_status ssf_batch_destroy(ssf_batch* b);
@@ -253,6 +256,12 @@ ssf_status ssf_batch_destroy(ssf_batch* b);
 /* Host helper: clamped uniform cubic B-spline basis on [a, b] with M >= 4
  * functions evaluated at z[0..nz-1]; B_out is (nz, M) row-major, FP64. */
 ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int32_t nz, double* B_out);
+/* Host helper: profiles x_k(z) = sum_m coeffs[k][m] B_m(z) of the same basis
+ * for nsets coefficient sets: out is (nsets, nz) row-major, FP64.  With
+ * ssf_profile_grad (the transpose of this map) it is the parameterisation of
+ * the guide centres whose gradient the adjoint gives. */
+ssf_status ssf_bspline_eval(int32_t M, double a, double b, const double* coeffs, int32_t nsets, const double* z,
+                            int32_t nz, double* out);
 
 const char* ssf_status_string(ssf_status s);
 const char* ssf_last_error(void);

@@ -87,8 +87,19 @@ def _load():
         lib.orc_adjoint_ctap.argtypes = [dp, ip, dp, dp, ctypes.c_int, dp, dp, dp,
                                          ctypes.c_double, ctypes.c_long, ctypes.c_double,
                                          dp, dp, dp]
+        lib.orc_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
+
+
+def threads():
+    """Threads the oracle's parallel loops use (results do not depend on it)."""
+    return int(_load().orc_threads())
+
+
+def set_threads(n):
+    _load().orc_set_threads(int(n))
 
 
 def _dp(a):

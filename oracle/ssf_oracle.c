@@ -46,6 +46,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -587,4 +590,25 @@ void orc_adjoint_ctap(const double *psi0_, const int *n, const double *lo, const
         potential_half(lam, V, tot, -dt, 0);                 /* A^dagger */
     }
     free(u); free(lam); free(states); free(V);
+}
+
+/* Threads of the parallel loops (over independent pencils and planes: the
+ * results do not depend on the count). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

@@ -20,7 +20,7 @@ import numpy as np
 from . import _ssf
 from ._ssf import OBS_DTYPE, SSF_C64, SSF_C128, SSF_IMAG, SSF_REAL, SSFError
 
-__all__ = ["Solver", "Batch", "SSFError", "OBS_DTYPE", "supported_length", "bspline_basis", "load"]
+__all__ = ["Solver", "Batch", "SSFError", "OBS_DTYPE", "supported_length", "bspline_basis", "bspline_eval", "load"]
 
 
 def load():
@@ -39,6 +39,19 @@ def bspline_basis(M, a, b, z):
     _ssf.call("ssf_bspline_basis", int(M), float(a), float(b), z.ctypes.data_as(dp), z.shape[0],
               B.ctypes.data_as(dp))
     return B
+
+
+def bspline_eval(M, a, b, coeffs, z):
+    """(len(coeffs), len(z)) profiles sum_m coeffs[k, m] B_m(z) of the same basis (host, FP64)."""
+    c = np.ascontiguousarray(np.atleast_2d(coeffs), dtype=np.float64)
+    if c.shape[1] != int(M):
+        raise ValueError("coeffs must have M = %d columns" % int(M))
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty((c.shape[0], z.shape[0]), dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _ssf.call("ssf_bspline_eval", int(M), float(a), float(b), c.ctypes.data_as(dp), c.shape[0],
+              z.ctypes.data_as(dp), z.shape[0], out.ctypes.data_as(dp))
+    return out
 
 
 def _torch():
@@ -356,6 +369,8 @@ class Batch:
                                  % (i, self.tdtype, s, self.device))
             self._ptrs[i] = t.data_ptr()
         ob = ctypes.c_void_p(obs_buf.data_ptr()) if obs_buf is not None else ctypes.c_void_p(0)
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        _ssf.call("ssf_batch_set_stream", self.h, ctypes.c_void_p(stream))
         _ssf.call("ssf_batch_run", self.h, self._ptrs, int(nsteps), float(dt), int(chunk), ob)
 
     def read_obs(self, buf):

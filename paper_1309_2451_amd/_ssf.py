@@ -37,7 +37,7 @@ EXPORTS = (
     "ssf_tune", "ssf_set_tiles", "ssf_get_tiles", "ssf_step", "ssf_fft", "ssf_observables",
     "ssf_obs_read", "ssf_density_xz", "ssf_sync", "ssf_copy", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
-    "ssf_batch_info", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_status_string", "ssf_last_error",
+    "ssf_batch_info", "ssf_batch_set_stream", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_bspline_eval", "ssf_status_string", "ssf_last_error",
 )
 
 
@@ -120,8 +120,10 @@ def load():
         "ssf_batch_run": ([hp, vp, i64, dbl, i64, vp], i32),
         "ssf_batch_tune": ([hp, i32], i32),
         "ssf_batch_info": ([hp, ctypes.POINTER(i32), vp], i32),
+        "ssf_batch_set_stream": ([hp, vp], i32),
         "ssf_batch_destroy": ([hp], i32),
         "ssf_bspline_basis": ([i32, dbl, dbl, dp, i32, dp], i32),
+        "ssf_bspline_eval": ([i32, dbl, dbl, dp, i32, dp, i32, dp], i32),
         "ssf_status_string": ([i32], ctypes.c_char_p),
         "ssf_last_error": ([], ctypes.c_char_p),
     }

@@ -1022,13 +1022,34 @@ inline int device_cus() {
   return cus;
 }
 
+// Workgroups per compute unit of one kernel, cached per dynamic LDS size (the
+// x passes hold 3 Ny doubles of guide table in dynamic LDS, so grids with
+// another Ny can fit a different number of workgroups).  A full cache is
+// bypassed, not evicted.
+struct OccCache {
+  static constexpr int SLOTS = 8;
+  size_t dyn[SLOTS] = {};
+  int occ[SLOTS] = {};
+  int used = 0;
+};
+
 template <typename K>
-hipError_t launch_persistent(K kernel, int wg, size_t dyn, PassArgs a, dim3 tiles, hipStream_t st, int& occ) {
-  if (occ <= 0) {
-    int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kernel, wg, dyn) != hipSuccess || o < 1) o = 1;
-    occ = o;
+int occupancy(K kernel, int wg, size_t dyn, OccCache& c) {
+  for (int i = 0; i < c.used; ++i)
+    if (c.dyn[i] == dyn) return c.occ[i];
+  int o = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kernel, wg, dyn) != hipSuccess || o < 1) o = 1;
+  if (c.used < OccCache::SLOTS) {
+    c.dyn[c.used] = dyn;
+    c.occ[c.used] = o;
+    ++c.used;
   }
+  return o;
+}
+
+template <typename K>
+hipError_t launch_persistent(K kernel, int wg, size_t dyn, PassArgs a, dim3 tiles, hipStream_t st, OccCache& oc) {
+  const int occ = occupancy(kernel, wg, dyn, oc);
   a.tiles_x = (int)tiles.x;
   a.tiles_y = (int)tiles.y;
   const long long ntiles = (long long)tiles.x * tiles.y * (a.ninst > 0 ? a.ninst : 1);
@@ -1044,7 +1065,7 @@ template <typename S, int N, int DT, int VAR, bool B>
 hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t st) {
   constexpr int SX = Shape<N>::sx(DT, VAR), SO = Shape<N>::so(DT, VAR), SM = Shape<N>::sm(DT, VAR);
   constexpr int WGS = PassGeom<S, N, SX, SO, false, SM>::WG;
-  static int occ[4] = {0, 0, 0, 0};
+  static OccCache occ[4];
   switch (kind) {
     case STRIDED_FWD:
       if (a.post == 0)
@@ -1073,7 +1094,7 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
   constexpr int CR = Shape<N>::cr();
   constexpr int WGC = PassGeom<S, N, CR, 1, true, 1>::WG;
   const size_t dync = sizeof(double) * MAX_GUIDES * (size_t)a.ny;
-  static int occ[4] = {0, 0, 0, 0};
+  static OccCache occ[4];
   const bool lean_x = a.pre == 0 && a.post == 0 && !a.imag && (a.vkind == V_CTAP || a.vkind == V_NONE);
   switch (kind) {
     case CONTIG_FWD:

@@ -1150,40 +1150,72 @@ ssf_status ssf_profile_grad(ssf_handle* h, const double* G_dev, int32_t nguides,
   return SSF_OK;
 }
 
-ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int32_t nz, double* B_out) {
-  if (M < 4 || !(b > a) || nz < 0 || (nz > 0 && (!z || !B_out))) return fail(SSF_E_INVALID, "bad B-spline arguments");
+}  // extern "C"
+
+namespace {
+
+// Clamped uniform cubic knots over [a, b] with M basis functions.
+std::vector<double> bspline_knots(int M, double a, double b) {
   const int nk = M + 4, nseg = M - 3;
-  std::vector<double> t(nk), N0(nk);
+  std::vector<double> t(nk);
   for (int i = 0; i < 4; ++i) { t[i] = a; t[nk - 1 - i] = b; }
   for (int i = 1; i < nseg; ++i) t[3 + i] = a + (b - a) * (double)i / (double)nseg;
+  return t;
+}
+
+// The M basis functions at u (row[0..M-1]): the knot span, then the de Boor
+// triangle of its 4 nonzero functions.
+void bspline_row(const std::vector<double>& t, int M, double b, double u, double* row) {
+  for (int m = 0; m < M; ++m) row[m] = 0.0;
+  if (u >= b) {
+    row[M - 1] = 1.0;
+    return;
+  }
+  int span = 3;
+  while (span < M - 1 && u >= t[span + 1]) ++span;
+  double Nl[4] = {1.0, 0.0, 0.0, 0.0};
+  double left[4], right[4];
+  for (int d = 1; d <= 3; ++d) {
+    left[d] = u - t[span + 1 - d];
+    right[d] = t[span + d] - u;
+    double saved = 0.0;
+    for (int r = 0; r < d; ++r) {
+      const double den = right[r + 1] + left[d - r];
+      const double tmp = den > 0.0 ? Nl[r] / den : 0.0;
+      Nl[r] = saved + right[r + 1] * tmp;
+      saved = left[d - r] * tmp;
+    }
+    Nl[d] = saved;
+  }
+  for (int r = 0; r < 4; ++r) {
+    const int m = span - 3 + r;
+    if (m >= 0 && m < M) row[m] = Nl[r];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ssf_status ssf_bspline_basis(int32_t M, double a, double b, const double* z, int32_t nz, double* B_out) {
+  if (M < 4 || !(b > a) || nz < 0 || (nz > 0 && (!z || !B_out))) return fail(SSF_E_INVALID, "bad B-spline arguments");
+  const std::vector<double> t = bspline_knots(M, a, b);
+  for (int iz = 0; iz < nz; ++iz) bspline_row(t, M, b, z[iz], B_out + (long long)iz * M);
+  return SSF_OK;
+}
+
+ssf_status ssf_bspline_eval(int32_t M, double a, double b, const double* coeffs, int32_t nsets, const double* z,
+                            int32_t nz, double* out) {
+  if (M < 4 || !(b > a) || nz < 0 || nsets < 0 || (nz > 0 && nsets > 0 && (!z || !out || !coeffs)))
+    return fail(SSF_E_INVALID, "bad B-spline arguments");
+  const std::vector<double> t = bspline_knots(M, a, b);
+  std::vector<double> row(M);
   for (int iz = 0; iz < nz; ++iz) {
-    const double u = z[iz];
-    double* row = B_out + (long long)iz * M;
-    if (u >= b) {
-      for (int m = 0; m < M; ++m) row[m] = m == M - 1 ? 1.0 : 0.0;
-      continue;
-    }
-    // locate the knot span, then the de Boor triangle of the 4 nonzero functions
-    int span = 3;
-    while (span < M - 1 && u >= t[span + 1]) ++span;
-    double Nl[4] = {1.0, 0.0, 0.0, 0.0};
-    double left[4], right[4];
-    for (int d = 1; d <= 3; ++d) {
-      left[d] = u - t[span + 1 - d];
-      right[d] = t[span + d] - u;
-      double saved = 0.0;
-      for (int r = 0; r < d; ++r) {
-        const double den = right[r + 1] + left[d - r];
-        const double tmp = den > 0.0 ? Nl[r] / den : 0.0;
-        Nl[r] = saved + right[r + 1] * tmp;
-        saved = left[d - r] * tmp;
-      }
-      Nl[d] = saved;
-    }
-    for (int m = 0; m < M; ++m) row[m] = 0.0;
-    for (int r = 0; r < 4; ++r) {
-      const int m = span - 3 + r;
-      if (m >= 0 && m < M) row[m] = Nl[r];
+    bspline_row(t, M, b, z[iz], row.data());
+    for (int k = 0; k < nsets; ++k) {
+      double v = 0.0;
+      for (int m = 0; m < M; ++m) v += coeffs[(long long)k * M + m] * row[m];
+      out[(long long)k * nz + iz] = v;
     }
   }
   return SSF_OK;
@@ -1406,6 +1438,12 @@ ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf
   return SSF_OK;
 }
 
+ssf_status ssf_batch_set_stream(ssf_batch* b, void* hip_stream) {
+  if (!b) return fail(SSF_E_INVALID, "null batch");
+  b->user = (hipStream_t)hip_stream;
+  return SSF_OK;
+}
+
 ssf_status ssf_batch_destroy(ssf_batch* b) {
   batch_free(b);
   return SSF_OK;
@@ -1439,16 +1477,28 @@ ssf_status ssf_batch_run(ssf_batch* b, void* const* psi, int64_t nsteps, double 
   if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
   HIP_TRY(hipSetDevice(b->device));
   const size_t esize = b->dtype == SSF_C64 ? 8 : 16;
-  // descriptors: field pointers of this call (uploaded only when they change)
+  // descriptors: field pointers of this call (uploaded only when they change).
+  // Every pass of the previous call, its graph replays and its observation
+  // kernels included, reads the old descriptors; all of that work ends on the
+  // capture stream, so the upload waits for it (and for the group streams).
+  for (auto& G : b->groups)
+    for (size_t k = 0; k < G.members.size(); ++k) {
+      void* p = psi[G.members[k]];
+      if (!p || ((uintptr_t)p) % (esize / 2) != 0) return fail(SSF_E_INVALID, "field pointer null or misaligned");
+    }
+  bool waited = false;
   for (auto& G : b->groups) {
     bool changed = false;
     for (size_t k = 0; k < G.members.size(); ++k) {
       void* p = psi[G.members[k]];
-      if (!p || ((uintptr_t)p) % (esize / 2) != 0) return fail(SSF_E_INVALID, "field pointer null or misaligned");
       if (G.inst[k].in != p) { G.inst[k].in = p; G.inst[k].out = p; changed = true; }
     }
     if (changed) {
-      HIP_TRY(hipStreamSynchronize(G.stream));
+      if (!waited) {
+        HIP_TRY(hipStreamSynchronize(b->cap));
+        for (auto& H : b->groups) HIP_TRY(hipStreamSynchronize(H.stream));
+        waited = true;
+      }
       HIP_TRY(hipMemcpy(G.d_inst, G.inst.data(), sizeof(ssf::InstDesc) * G.inst.size(), hipMemcpyHostToDevice));
     }
   }

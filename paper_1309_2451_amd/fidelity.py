@@ -18,7 +18,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import Solver, bspline_basis
+from . import Solver, bspline_basis, bspline_eval
 
 
 class FidelityProblem:
@@ -48,6 +48,8 @@ class FidelityProblem:
         self.nsteps = int(nsteps)
         self.every = int(every)
         z = solver.lo[2] + np.arange(solver.n[2]) * (solver.hi[2] - solver.lo[2]) / solver.n[2]
+        self.z = z
+        self.zrange = (float(zrange[0]), float(zrange[1]))
         self.B = bspline_basis(self.M, zrange[0], zrange[1], z)               # (Nz, M), host
         self.B_dev = torch.from_numpy(self.B).to(solver.device).contiguous()
         solver.set_partition(x_lo, x_hi)
@@ -62,10 +64,11 @@ class FidelityProblem:
     def profile(self, coeffs):
         """(3, Nz) guide centres for coefficients of shape (len(moving), M)."""
         c = np.asarray(coeffs, dtype=np.float64).reshape(len(self.moving), self.M)
+        prof = bspline_eval(self.M, self.zrange[0], self.zrange[1], c, self.z)   # the library's map
         xc = np.zeros((3, self.s.n[2]))
         xc[1] = self.x_mid
         for k, g in enumerate(self.moving):
-            xc[g] = self.B @ c[k]
+            xc[g] = prof[k]
         return xc
 
     def forward(self, coeffs) -> float:

@@ -96,3 +96,21 @@ def test_bspline_host_helper_matches_oracle(M):
     assert np.max(np.abs(B - Bo)) < 1e-14
     with pytest.raises(ssfpkg.SSFError):
         ssfpkg.bspline_basis(3, -1.0, 1.0, z)
+
+
+@pytest.mark.parametrize("M", [4, 16])
+def test_bspline_profile_helper_matches_oracle(M):
+    """The guide-centre map x_k(z) = sum_m c_km B_m(z) that the gradient
+    workload evaluates in the library, against the oracle's basis times the
+    coefficients (the transpose of the map ssf_profile_grad applies)."""
+    import oracle
+    z = np.linspace(-48.0, 48.0, 257)
+    c = np.random.default_rng(M).standard_normal((2, M))
+    prof = ssfpkg.bspline_eval(M, -48.0, 48.0, c, z)
+    Bo = oracle.bspline_basis(M, -48.0, 48.0, z)
+    assert prof.shape == (2, z.size)
+    assert np.max(np.abs(prof - c @ Bo.T)) < 1e-13 * np.max(np.abs(c))
+    with pytest.raises(ValueError):
+        ssfpkg.bspline_eval(M, -48.0, 48.0, np.zeros((2, M + 1)), z)
+    lib = _lib()
+    assert lib.ssf_bspline_eval(3, -1.0, 1.0, None, 1, None, 1, None) == _ssf.SSF_E_INVALID

@@ -181,3 +181,36 @@ def test_batch_sweep_full_size_instances_vs_oracle():
         assert abs(rec[i]["norm"] - o["norm"]) < 1e-12
         assert abs(rec[i]["pop"][0] - o["p1"]) < 1e-12
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_two_runs_on_a_side_stream_without_host_sync(dtype):
+    """Two runs with different field lists enqueued back to back on a side
+    stream, no host synchronisation between them: the second run's
+    descriptor upload must wait for the first run's graph replays, so each
+    field list evolves exactly as on single handles."""
+    inst = _instances()
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    dt, chunk = 0.01, 4
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b = _batch(inst, dtype)
+        fa = [torch.from_numpy(p).to(tdt).to(DEV).contiguous() for _, _, p in inst]
+        fb = [torch.from_numpy(p).to(tdt).to(DEV).contiguous() * 0.5 for _, _, p in inst]
+        ra = [f.clone() for f in fa]
+        rb = [f.clone() for f in fb]
+        say("side stream: run A (40 steps), run B (12 steps)", dtype)
+        b.run(fa, 40, dt, chunk=chunk)
+        b.run(fb, 12, dt, chunk=chunk)
+    side.synchronize()
+    for i, (g, gd, _) in enumerate(inst):
+        s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+        s.set_guides(gd.v0, gd.sigma, gd.xc)
+        s.set_partition(gd.x_lo, gd.x_hi)
+        s.step(ra[i], 40, dt, obs_every=chunk)
+        s.step(rb[i], 12, dt, obs_every=chunk)
+        torch.cuda.synchronize()
+        assert torch.equal(fa[i], ra[i]), "run A, instance %d" % i
+        assert torch.equal(fb[i], rb[i]), "run B, instance %d" % i
+        s.close()
+    b.close()

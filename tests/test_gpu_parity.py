@@ -427,19 +427,35 @@ def test_gradient_workload_copy_vs_oracle_adjoint(dtype):
     scale = np.max(np.abs(grad_ref))
     say("F", float(F.detach()), F_ref, "max|grad|", scale)
     assert F_ref > 5e-5                       # the packet is in the coupling region
+    err = np.max(np.abs(grad - grad_ref))
+    say("max |grad - oracle| / max|grad|", err / scale)
+
+    def central(k, m, h):
+        cp, cm = cfg["coeffs"].copy(), cfg["coeffs"].copy()
+        cp[k, m] += h
+        cm[k, m] -= h
+        return (prob.forward(cp) - prob.forward(cm)) / (2 * h)
+
+    # the two largest gradient components (a relative check needs |g| well above the rounding of F / h)
+    top = np.dstack(np.unravel_index(np.argsort(-np.abs(grad_ref), axis=None)[:2], grad_ref.shape))[0]
+    h = 1e-3
     if dtype == "c128":
         assert abs(float(F.detach()) - F_ref) < 1e-12
-        assert np.max(np.abs(grad - grad_ref)) < 1e-9 * scale
-        for k, m in [(0, 5), (1, 8)]:
-            h = 1e-3
-            cp, cm = cfg["coeffs"].copy(), cfg["coeffs"].copy()
-            cp[k, m] += h
-            cm[k, m] -= h
-            fd = (prob.forward(cp) - prob.forward(cm)) / (2 * h)
-            assert abs(fd - grad[k, m]) < 1e-4 * scale, (k, m, fd, grad[k, m])
+        assert err < 1e-9 * scale
+        for k, m in top:
+            d1, d2 = central(k, m, h), central(k, m, h / 2)
+            rich = (4.0 * d2 - d1) / 3.0                # O(h^4): removes the h^2 term of both
+            say("central differences (%d, %d): h %.6e, h/2 %.6e, extrapolated %.6e, adjoint %.6e"
+                % (k, m, d1, d2, rich, grad[k, m]))
+            assert abs(rich - grad[k, m]) <= 1e-5 * abs(grad[k, m]), (k, m, rich, grad[k, m])
+            assert abs(d2 - grad[k, m]) <= 1e-3 * abs(grad[k, m]), (k, m, d2, grad[k, m])
     else:
         assert abs(float(F.detach()) - F_ref) < 1e-6 * max(F_ref, 1e-3)
-        assert np.max(np.abs(grad - grad_ref)) < 1e-3 * scale
+        assert err < 1e-4 * scale
+        for k, m in top:
+            d1 = central(k, m, h)
+            say("c64 central difference (%d, %d): %.6e, adjoint %.6e" % (k, m, d1, grad[k, m]))
+            assert abs(d1 - grad[k, m]) <= max(2e-2 * abs(grad[k, m]), 1e-3 * scale), (k, m, d1, grad[k, m])
     s.close()
 
 
