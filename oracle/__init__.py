@@ -36,6 +36,11 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                              Greville coefficients, support and endpoint values
   adjoint_ctap               pinned: central finite differences of the forward
                              oracle (O(h^2) check at two step sizes)
+  chip_field_points /        pinned: infinite straight wire mu0 I / (2 pi rho), the
+  chip_potential(_points)    guide height r0 = mu0 I / (2 pi B_b) of a wire under a
+                             bias field (Sec. III), segment additivity, mirror
+                             symmetry of straight wires, the harmonic transverse
+                             frequency of a single-wire guide, the bare V_z trap
 """
 from __future__ import annotations
 
@@ -87,10 +92,61 @@ def _load():
         lib.orc_adjoint_ctap.argtypes = [dp, ip, dp, dp, ctypes.c_int, dp, dp, dp,
                                          ctypes.c_double, ctypes.c_long, ctypes.c_double,
                                          dp, dp, dp]
+        chip = [ctypes.c_int, ip, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.orc_chip_potential_points.argtypes = [dp, dp, ctypes.c_long] + chip + [ctypes.c_double] * 3
+        lib.orc_chip_potential.argtypes = [dp, ip, dp, dp] + chip + [ctypes.c_double] * 3
+        lib.orc_chip_field_points.argtypes = [dp, dp, ctypes.c_long] + chip
         lib.orc_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
+
+
+def _wires(paths, currents):
+    """(nwires, npts int array, concatenated (x, z) path array, currents) for the C side."""
+    paths = [np.ascontiguousarray(p, dtype=np.float64).reshape(-1, 2) for p in paths]
+    npts = np.array([p.shape[0] for p in paths], dtype=np.int32)
+    flat = np.ascontiguousarray(np.concatenate([p.ravel() for p in paths]))
+    cur = np.ascontiguousarray(currents, dtype=np.float64)
+    assert cur.shape == (len(paths),) and np.all(npts >= 2)
+    return len(paths), npts, flat, cur
+
+
+def chip_field_points(pts, paths, currents, b_bias, b_ip, length_unit):
+    """Magnetic field (tesla), shape (m, 3), of thin wires along the polylines
+    `paths` (each (k, 2): x, z in the chip plane y = 0) with `currents`, plus
+    b_bias along +x and b_ip along +z, at points pts (m, 3) = (x, y, z)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    nw, npts, flat, cur = _wires(paths, currents)
+    out = np.zeros((pts.shape[0], 3))
+    _load().orc_chip_field_points(_dp(out), _dp(pts), pts.shape[0], nw,
+                                  npts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(flat), _dp(cur),
+                                  float(b_bias), float(b_ip), float(length_unit))
+    return out
+
+
+def chip_potential_points(pts, paths, currents, b_bias, b_ip, length_unit, mu_over_e0, omega_z, z_c):
+    """Atom-chip potential mu_over_e0 (|B| - b_ip) + omega_z^2 (z - z_c)^2 / 2 at points (m, 3)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    nw, npts, flat, cur = _wires(paths, currents)
+    out = np.zeros(pts.shape[0])
+    _load().orc_chip_potential_points(_dp(out), _dp(pts), pts.shape[0], nw,
+                                      npts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(flat), _dp(cur),
+                                      float(b_bias), float(b_ip), float(length_unit), float(mu_over_e0),
+                                      float(omega_z), float(z_c))
+    return out
+
+
+def chip_potential(shape_zyx, lo, hi, paths, currents, b_bias, b_ip, length_unit, mu_over_e0, omega_z, z_c):
+    """The atom-chip potential on a (nz, ny, nx) grid."""
+    n, lo, hi = _grid_from(shape_zyx, lo, hi)
+    nw, npts, flat, cur = _wires(paths, currents)
+    V = np.zeros(tuple(shape_zyx))
+    _load().orc_chip_potential(_dp(V), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(lo), _dp(hi), nw,
+                               npts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(flat), _dp(cur),
+                               float(b_bias), float(b_ip), float(length_unit), float(mu_over_e0), float(omega_z),
+                               float(z_c))
+    return V
 
 
 def threads():

@@ -453,6 +453,128 @@ void orc_ctap_potential(double *V, const int *n, const double *lo, const double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Atom-chip potential: thin current-carrying wires on the chip surface plus  */
+/* homogeneous bias and offset fields (Sec. III) and the longitudinal         */
+/* harmonic trap V_z (Sec. III, last paragraphs).                             */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Magnetic field (tesla) of the wires alone at point (px, py, pz).  Lengths
+ * are in units of length_unit metres.  Wire w is the polyline through the
+ * points (path[2k], 0, path[2k+1]) (x and z; the wires lie in the chip plane
+ * y = 0) carrying current[w] amperes from its first point to its last.
+ *
+ * Biot-Savart law (Sec. III) for one straight segment from A to B, written
+ * out: with L = B - A, a = P - A, b = P - B, the line integral of
+ * dl x r_hat / r^2 over the segment equals
+ *     (L x a) / |L x a|^2 * (L.a / |a| - L.b / |b|),
+ * the classic finite-wire result (mu0 I / (4 pi rho)) (cos t1 - cos t2) along
+ * the azimuthal direction, with rho = |L x a| / |L| the distance from the
+ * segment's line.  Points on that line get no contribution from it.
+ */
+static void wire_field(double px, double py, double pz, int nwires, const int *npts,
+                       const double *path, const double *current, double length_unit, double *B)
+{
+    const double mu0_4pi = 1.25663706212e-6 / (4.0 * 3.14159265358979323846);
+    double bx = 0.0, by = 0.0, bz = 0.0;
+    const double *pp = path;
+    for (int w = 0; w < nwires; ++w) {
+        double k = mu0_4pi * current[w] / length_unit;
+        for (int s = 0; s + 1 < npts[w]; ++s) {
+            double Ax = pp[2 * s], Az = pp[2 * s + 1];
+            double Bx = pp[2 * s + 2], Bz = pp[2 * s + 3];
+            double Lx = Bx - Ax, Ly = 0.0, Lz = Bz - Az;
+            double ax = px - Ax, ay = py, az = pz - Az;
+            double bxv = px - Bx, byv = py, bzv = pz - Bz;
+            /* c = L x a */
+            double cx = Ly * az - Lz * ay;
+            double cy = Lz * ax - Lx * az;
+            double cz = Lx * ay - Ly * ax;
+            double c2 = cx * cx + cy * cy + cz * cz;
+            if (c2 == 0.0)
+                continue;
+            double la = (Lx * ax + Ly * ay + Lz * az) / sqrt(ax * ax + ay * ay + az * az);
+            double lb = (Lx * bxv + Ly * byv + Lz * bzv) / sqrt(bxv * bxv + byv * byv + bzv * bzv);
+            double f = k * (la - lb) / c2;
+            bx += f * cx;
+            by += f * cy;
+            bz += f * cz;
+        }
+        pp += 2 * npts[w];
+    }
+    B[0] = bx;
+    B[1] = by;
+    B[2] = bz;
+}
+
+/*
+ * The potential from the wires' field Bw at a point:
+ *     V = mu_over_e0 (|B| - b_ip) + omega_z^2 (z - z_c)^2 / 2,
+ * B = Bw + (b_bias, 0, b_ip), the magnetic energy of a low-field-seeking
+ * atom (magnetic moment mu, energy unit E0, so mu_over_e0 = mu / E0 per
+ * tesla) measured from its value at a field of magnitude b_ip, plus the
+ * longitudinal trap of frequency omega_z (in inverse time units) centred at
+ * z_c.  |B| - b_ip is evaluated as (|B|^2 - b_ip^2) / (|B| + b_ip) with
+ * |B|^2 - b_ip^2 = Bx^2 + By^2 + Bwz (Bwz + 2 b_ip): the same number without
+ * the cancellation of two nearly equal magnitudes at the guide centres.
+ */
+static double chip_value(const double *Bw, double dz, double b_bias, double b_ip, double mu_over_e0,
+                         double omega_z)
+{
+    double bx = Bw[0] + b_bias, by = Bw[1], bz = Bw[2] + b_ip;
+    double mag = sqrt(bx * bx + by * by + bz * bz);
+    double excess = (bx * bx + by * by + Bw[2] * (Bw[2] + 2.0 * b_ip)) / (mag + b_ip);
+    return mu_over_e0 * excess + 0.5 * omega_z * omega_z * dz * dz;
+}
+
+/* V at m points pts[3i..3i+2] = (x, y, z). */
+void orc_chip_potential_points(double *V, const double *pts, long m, int nwires, const int *npts,
+                               const double *path, const double *current, double b_bias, double b_ip,
+                               double length_unit, double mu_over_e0, double omega_z, double z_c)
+{
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < m; ++i) {
+        double Bw[3];
+        wire_field(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], nwires, npts, path, current, length_unit, Bw);
+        V[i] = chip_value(Bw, pts[3 * i + 2] - z_c, b_bias, b_ip, mu_over_e0, omega_z);
+    }
+}
+
+/* The same potential on the whole grid, (nz, ny, nx). */
+void orc_chip_potential(double *V, const int *n, const double *lo, const double *hi, int nwires,
+                        const int *npts, const double *path, const double *current, double b_bias,
+                        double b_ip, double length_unit, double mu_over_e0, double omega_z, double z_c)
+{
+    grid_t g = make_grid(n, lo, hi);
+    int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    #pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z) {
+        double zc = grid_coord(&g, 2, z);
+        for (int y = 0; y < ny; ++y) {
+            double yc = grid_coord(&g, 1, y);
+            for (int x = 0; x < nx; ++x) {
+                double Bw[3];
+                wire_field(grid_coord(&g, 0, x), yc, zc, nwires, npts, path, current, length_unit, Bw);
+                V[((long)z * ny + y) * nx + x] = chip_value(Bw, zc - z_c, b_bias, b_ip, mu_over_e0, omega_z);
+            }
+        }
+    }
+}
+
+/* The total field Bw + (b_bias, 0, b_ip) (tesla) at m points, (m, 3). */
+void orc_chip_field_points(double *Bout, const double *pts, long m, int nwires, const int *npts,
+                           const double *path, const double *current, double b_bias, double b_ip,
+                           double length_unit)
+{
+    for (long i = 0; i < m; ++i) {
+        wire_field(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], nwires, npts, path, current, length_unit,
+                   Bout + 3 * i);
+        Bout[3 * i] += b_bias;
+        Bout[3 * i + 2] += b_ip;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Clamped uniform cubic B-splines (guide-centre profile parameterisation).  */
 /* ------------------------------------------------------------------------ */
 

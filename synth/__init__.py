@@ -221,3 +221,114 @@ def config5(n=(128, 128, 256), M=16):
                 coeffs=np.stack([c1, c3]), v0=np.full(3, 40.0), sigma=np.full(3, 0.6),
                 x_lo=-1.5, x_hi=1.5, dt=0.004, steps=4000, ckpt_every=64,
                 z0=-24.0, zwidth=4.0, kz=3.0)
+
+
+# ---------------------------------------------------------------------------
+# Atom chip (Sec. III): three thin wires on the chip surface, a bias field
+# across them, an offset field along them, a 6Li atom and a longitudinal
+# harmonic trap.  Only parameters and geometry here; the field and the
+# potential are computed by the oracle and by the library.
+# ---------------------------------------------------------------------------
+
+HBAR = 1.054571817e-34           # J s (CODATA 2018)
+ATOMIC_MASS = 1.66053906660e-27  # kg
+MASS_LI6 = 6.0151228874 * ATOMIC_MASS
+MU_B = 9.2740100783e-24          # J / T; 6Li |F=3/2, m_F=3/2>: g_F m_F = 1
+
+
+def chip_units(length_unit=1e-6, mass=MASS_LI6, moment=MU_B):
+    """hbar = m = 1 units with lengths in `length_unit` metres: time unit
+    t0 = m L0^2 / hbar (s), energy unit e0 = hbar / t0 (J), and the magnetic
+    moment in energy units per tesla."""
+    t0 = mass * length_unit ** 2 / HBAR
+    e0 = HBAR / t0
+    return dict(length_unit=length_unit, t0=t0, e0=e0, mu_over_e0=moment / e0)
+
+
+def chip_separation(z, z_close, sep0=7.0, sep_min=4.3, bend=700.0):
+    """Distance of an outer wire from the middle one along z: sep0 far away,
+    sep_min at z_close, a raised-cosine approach and retreat over `bend`."""
+    u = (np.asarray(z, dtype=np.float64) - (z_close - 0.5 * bend)) / bend
+    c = np.where((u > 0.0) & (u < 1.0), 0.5 * (1.0 - np.cos(2.0 * np.pi * u)), 0.0)
+    return sep0 - (sep0 - sep_min) * c
+
+
+def chip_wire_paths(sep0=7.0, sep_min=4.3, xi=50.0, z_mid=500.0, bend=700.0, ds=1.0, ext=1.0e5,
+                    zlen=1000.0, intuitive=False):
+    """Polylines (k, 2) of (x, z) in micrometres for the left, middle and right
+    wires.  The middle wire runs straight along x = 0.  The outer wires run at
+    -/+ sep0 and approach the middle one to sep_min; the left wire stays
+    straight for xi longer, so the right pair comes closest first
+    (counter-intuitive order for an atom moving towards +z); intuitive=True
+    swaps the two.  Straight ends continue to z = -ext and z = zlen + ext, so
+    both ends of the simulated box see the same straight, evenly spaced wires."""
+    z_right = z_mid - 0.5 * xi
+    z_left = z_mid + 0.5 * xi
+    if intuitive:
+        z_right, z_left = z_left, z_right
+    paths = []
+    for sign, zc in ((-1.0, z_left), (None, None), (+1.0, z_right)):
+        if sign is None:
+            paths.append(np.array([[0.0, -ext], [0.0, zlen + ext]]))
+            continue
+        z0, z1 = zc - 0.5 * bend, zc + 0.5 * bend
+        zb = np.linspace(z0, z1, int(round(bend / ds)) + 1)
+        xb = sign * chip_separation(zb, zc, sep0, sep_min, bend)
+        pts = np.concatenate([[[sign * sep0, -ext]], np.stack([xb, zb], axis=1), [[sign * sep0, zlen + ext]]])
+        paths.append(pts)
+    return paths
+
+
+def chip_wire_x(paths, z):
+    """(3, len(z)) x positions of the wires in the planes z (linear along each polyline)."""
+    return np.stack([np.interp(z, p[:, 1], p[:, 0]) for p in paths])
+
+
+MU0 = 1.25663706212e-6           # T m / A (CODATA 2018)
+
+
+def chip_moment_for_period(units, b_bias=0.014, b_ip=0.03, current=0.1, period=0.2e-3):
+    """Magnetic moment over the energy unit (per tesla) that gives an isolated
+    straight-wire guide the transverse trap period `period` (s) in the harmonic
+    approximation: a wire with current I under a bias B_b has its field zero
+    at r0 = mu0 I / (2 pi B_b), where the transverse field grows with gradient
+    G = 2 pi B_b^2 / (mu0 I); with the offset field B_ip the energy rises as
+    mu G^2 r^2 / (2 B_ip), so omega^2 = (mu/E0) G^2 / B_ip in units with
+    hbar = m = 1."""
+    G = 2.0 * np.pi * b_bias ** 2 / (MU0 * current) * units["length_unit"]   # tesla per length unit
+    omega = 2.0 * np.pi * units["t0"] / period
+    return omega ** 2 * b_ip / G ** 2
+
+
+def config_chip(i_mid=0.07, n=(256, 64, 1024), intuitive=False, i_outer=0.1):
+    """The three-wire 6Li atom chip of Secs. III and V: chip area 20 um x
+    1000 um (x, z), 4 um above the chip (y), wires 7 um apart approaching to
+    4.3 um, left wire straight 50 um longer, B_b = 0.014 T, B_ip = 0.03 T,
+    currents I_L = I_R = 0.1 A and I_M, longitudinal trap 2 pi x 5 Hz centred
+    at z = 500 um, dt = 1e-6 s for half a trap period (0.1 s, 10^5 steps).
+    Grid: x in [-10, 10) um, y from half a spacing above the chip surface
+    (so no grid point lies on a wire), z in [0, 1000) um."""
+    u = chip_units()
+    dy = 4.0 / n[1]
+    g = Grid(tuple(n), (-10.0, 0.5 * dy, 0.0), (10.0, 4.0 + 0.5 * dy, 1000.0))
+    paths = chip_wire_paths(intuitive=intuitive)
+    omega_z = 2.0 * np.pi * 5.0 * u["t0"]
+    dt = 1.0e-6 / u["t0"]
+    steps = int(round(0.1 / 1.0e-6))
+    xw = chip_wire_x(paths, g.axis(2))
+    # the stated fields give an isolated guide a ~270 kHz trap with the bare
+    # moment of 6Li, against the stated ~0.2 ms transverse period: the moment
+    # is scaled to the stated period (fields, currents and geometry unchanged)
+    mu = chip_moment_for_period(u, 0.014, 0.03, i_outer, 0.2e-3)
+    return dict(name="atom chip %dx%dx%d I_M=%g" % (tuple(n) + (i_mid,)), grid=g, paths=paths,
+                currents=np.array([i_outer, i_mid, i_outer]), b_bias=0.014, b_ip=0.03,
+                length_unit=u["length_unit"], mu_over_e0=mu, mu_over_e0_bare=u["mu_over_e0"],
+                omega_z=omega_z, z_c=500.0,
+                units=u, dt=dt, steps=steps, z0=16.0, zwidth=4.0,
+                x_lo=0.5 * (xw[0] + xw[1]), x_hi=0.5 * (xw[1] + xw[2]), wire_x=xw)
+
+
+def chip_sweep_currents():
+    """Middle-wire currents of the Fig. 6 sweep: 0.0672 A upwards in steps
+    of 0.001 A, ten values (0.0672 ... 0.0762 A)."""
+    return [round(0.0672 + 0.001 * k, 4) for k in range(10)]
