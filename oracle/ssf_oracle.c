@@ -244,11 +244,32 @@ static void kinetic_full(cplx *psih, const grid_t *g, double dt, int imag)
     }
 }
 
+/*
+ * Sums over the grid.  The observables are plain sums over every grid point
+ * (Sec. V: the population of a guide is the probability summed over its
+ * region); a running FP64 sum over the 10^7 - 10^8 points of a large grid
+ * carries a rounding error of order 1e-13 relative (one rounding per term),
+ * so every sum over the grid uses Neumaier's compensated summation, whose
+ * result lies within a few units in the last place of the exact sum: the
+ * running sum s and, in c, the rounding error of every addition.
+ */
+typedef struct { double s, c; } ksum_t;
+
+static void ksum_add(ksum_t *k, double x)
+{
+    double t = k->s + x;
+    if (fabs(k->s) >= fabs(x)) k->c += (k->s - t) + x;
+    else k->c += (x - t) + k->s;
+    k->s = t;
+}
+
+static double ksum_value(const ksum_t *k) { return k->s + k->c; }
+
 static double sum_abs2(const cplx *psi, long tot)
 {
-    double s = 0.0;
-    for (long i = 0; i < tot; ++i) s += creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
-    return s;
+    ksum_t s = {0.0, 0.0};
+    for (long i = 0; i < tot; ++i) ksum_add(&s, creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]));
+    return ksum_value(&s);
 }
 
 static void one_step(cplx *psi, const double *V, const grid_t *g, double dt, int imag)
@@ -335,7 +356,8 @@ void orc_observables(const double *psi_, const double *V, const int *n, const do
     int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     long tot = grid_points(&g);
     double dv = grid_dv(&g);
-    double s[8] = {0};
+    ksum_t s[8];
+    for (int q = 0; q < 8; ++q) s[q].s = s[q].c = 0.0;
     for (int z = 0; z < nz; ++z) {
         double zc = grid_coord(&g, 2, z);
         for (int y = 0; y < ny; ++y) {
@@ -344,19 +366,19 @@ void orc_observables(const double *psi_, const double *V, const int *n, const do
                 double xc = grid_coord(&g, 0, x);
                 long i = ((long)z * ny + y) * nx + x;
                 double r = creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
-                s[0] += r;
-                s[1] += xc * r; s[2] += yc * r; s[3] += zc * r;
-                if (xc < x_lo) s[4] += r;
-                else if (xc > x_hi) s[6] += r;
-                else s[5] += r;
-                if (V) s[7] += V[i] * r;
+                ksum_add(&s[0], r);
+                ksum_add(&s[1], xc * r); ksum_add(&s[2], yc * r); ksum_add(&s[3], zc * r);
+                if (xc < x_lo) ksum_add(&s[4], r);
+                else if (xc > x_hi) ksum_add(&s[6], r);
+                else ksum_add(&s[5], r);
+                if (V) ksum_add(&s[7], V[i] * r);
             }
         }
     }
     cplx *ph = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
     memcpy(ph, psi, sizeof(cplx) * (size_t)tot);
     fft3d(ph, nx, ny, nz, -1);
-    double kin = 0.0;
+    ksum_t kin = {0.0, 0.0};
     double Lx = g.hi[0] - g.lo[0], Ly = g.hi[1] - g.lo[1], Lz = g.hi[2] - g.lo[2];
     for (int z = 0; z < nz; ++z) {
         double kz = wavenumber(z, nz, Lz);
@@ -366,13 +388,13 @@ void orc_observables(const double *psi_, const double *V, const int *n, const do
                 double kx = wavenumber(x, nx, Lx);
                 long i = ((long)z * ny + y) * nx + x;
                 double r = creal(ph[i]) * creal(ph[i]) + cimag(ph[i]) * cimag(ph[i]);
-                kin += 0.5 * (kx * kx + ky * ky + kz * kz) * r;
+                ksum_add(&kin, 0.5 * (kx * kx + ky * ky + kz * kz) * r);
             }
         }
     }
     free(ph);
-    for (int q = 0; q < 7; ++q) out[q] = s[q] * dv;
-    out[7] = kin * dv / (double)tot + s[7] * dv;
+    for (int q = 0; q < 7; ++q) out[q] = ksum_value(&s[q]) * dv;
+    out[7] = ksum_value(&kin) * dv / (double)tot + ksum_value(&s[7]) * dv;
 }
 
 /*
@@ -388,18 +410,18 @@ void orc_populations_z(const double *psi_, const int *n, const double *lo, const
     const cplx *psi = (const cplx *)psi_;
     int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     double dv = grid_dv(&g);
-    double p[3] = {0.0, 0.0, 0.0};
+    ksum_t p[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 double xc = grid_coord(&g, 0, x);
                 long i = ((long)z * ny + y) * nx + x;
                 double r = creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
-                if (xc < x_lo[z]) p[0] += r;
-                else if (xc > x_hi[z]) p[2] += r;
-                else p[1] += r;
+                if (xc < x_lo[z]) ksum_add(&p[0], r);
+                else if (xc > x_hi[z]) ksum_add(&p[2], r);
+                else ksum_add(&p[1], r);
             }
-    for (int q = 0; q < 3; ++q) out[q] = p[q] * dv;
+    for (int q = 0; q < 3; ++q) out[q] = ksum_value(&p[q]) * dv;
 }
 
 /*

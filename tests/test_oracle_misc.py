@@ -128,3 +128,32 @@ def test_adjoint_matches_central_differences():
     h = 1e-4
     fd = (Fof(xc + h * d) - Fof(xc - h * d)) / (2 * h)
     assert abs(fd - np.sum(G * d)) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_observables_sums_are_exact_to_a_few_ulps_on_a_large_grid():
+    """The observables are plain sums over every grid point; on a grid of
+    2^22 points a running FP64 sum would be off by ~1e-14 relative or more.
+    The oracle's sums must agree with the exactly rounded sums of the same
+    products (math.fsum) to a few units in the last place."""
+    import math
+    g = synth.Grid((256, 128, 128), (-8.0, -8.0, -16.0), (8.0, 8.0, 16.0))
+    rng = np.random.default_rng(11)
+    psi = (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)) * 1e-3
+    V = rng.uniform(-40.0, 5.0, g.shape)
+    x_lo, x_hi = -1.3, 2.1
+    o = oracle.observables(psi, V, g.lo, g.hi, x_lo, x_hi)
+    dv = np.prod([(h - l) / n for n, l, h in zip(g.n, g.lo, g.hi)])
+    r = psi.real * psi.real + psi.imag * psi.imag
+    x = g.axis(0)
+    X = np.broadcast_to(x[None, None, :], g.shape)
+    exact = {
+        "norm": math.fsum(r.ravel()) * dv,
+        "mx": math.fsum((X * r).ravel()) * dv,
+        "p1": math.fsum(r[:, :, x < x_lo].ravel()) * dv,
+        "p3": math.fsum(r[:, :, x > x_hi].ravel()) * dv,
+        "p2": math.fsum(r[:, :, (x >= x_lo) & (x <= x_hi)].ravel()) * dv,
+    }
+    for key, val in exact.items():
+        assert abs(o[key] - val) <= 4e-16 * abs(val), (key, o[key], val)
+    # and the populations add up to the norm to the same accuracy
+    assert abs(o["p1"] + o["p2"] + o["p3"] - o["norm"]) <= 1e-15 * o["norm"]
