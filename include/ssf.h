@@ -175,6 +175,27 @@ ssf_status ssf_timing_read(ssf_handle* h, double* ms_total, int64_t* launches);
 ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time,
                     int64_t obs_every, ssf_obs* obs_dev);
 
+/* Allocation-free steps, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks and results (bitwise) as ssf_step, on
+ * the same handle and kernels; it never calls hipMalloc, hipFree or any
+ * allocating routine.  What a step sequence writes besides psi and obs_dev --
+ * the kinetic tables of dt (and dt/2 in the T/2-V-T/2 ordering), the FP64
+ * partial sums of the reducing passes and the device scale of imaginary
+ * time -- lives in one static device array per GPU of
+ * ssf_noalloc_scratch_bytes() bytes (16 MiB, held until the process ends).
+ * Every word of it is written before it is read within a call, so nothing is
+ * cleared between calls.  The array is shared by every handle on that GPU:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and give wrong results.  Per-pass timing (ssf_set_timing) is ignored
+ * during the call.  Errors as ssf_step, and INVALID when the grid needs more
+ * scratch than the maximum (ssf_noalloc_scratch_need(h) bytes: about 64 B per
+ * x-pass tile, e.g. 4 MiB for 512^3), checked before anything is enqueued. */
+ssf_status ssf_step_noalloc(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time,
+                            int64_t obs_every, ssf_obs* obs_dev);
+int64_t ssf_noalloc_scratch_bytes(void);
+int64_t ssf_noalloc_scratch_need(ssf_handle* h);
+
 /* Unnormalised 1-D transforms of psi (in place) along the axes in axis_mask
  * (bit 0 = x, 1 = y, 2 = z); inverse != 0 uses exp(+...). */
 ssf_status ssf_fft(ssf_handle* h, void* psi, int32_t axis_mask, int32_t inverse);

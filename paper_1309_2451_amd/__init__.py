@@ -224,6 +224,21 @@ class Solver:
             return self.read_obs(buf, nobs)
         return None
 
+    def step_noalloc(self, psi, nsteps, dt, imag=False, obs_every=0, obs_buf=None):
+        """As step(), through ssf_step_noalloc: the library allocates nothing
+        (its per-call buffers live in a static per-GPU scratch array).  Pass
+        obs_buf (from obs_buffer) to keep the call itself free of allocation;
+        without it a records buffer is allocated here by torch."""
+        self._sync_stream()
+        p = self._field(psi)
+        nobs = (int(nsteps) // int(obs_every)) if obs_every else 0
+        buf = obs_buf if obs_buf is not None else (self.obs_buffer(nobs) if nobs else None)
+        _ssf.call("ssf_step_noalloc", self.h, p, int(nsteps), float(dt), SSF_IMAG if imag else SSF_REAL,
+                  int(obs_every) if nobs else 0, ctypes.c_void_p(buf.data_ptr()) if buf is not None else None)
+        if nobs and obs_buf is None:
+            return self.read_obs(buf, nobs)
+        return None
+
     def fft(self, psi, axes=(0, 1, 2), inverse=False):
         self._sync_stream()
         mask = 0

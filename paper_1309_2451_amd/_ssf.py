@@ -38,6 +38,7 @@ EXPORTS = (
     "ssf_obs_read", "ssf_density_xz", "ssf_sync", "ssf_copy", "ssf_step_ckpt", "ssf_step_seq", "ssf_adjoint_init",
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
     "ssf_batch_info", "ssf_batch_set_stream", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_bspline_eval", "ssf_status_string", "ssf_last_error",
+    "ssf_step_noalloc", "ssf_noalloc_scratch_bytes", "ssf_noalloc_scratch_need",
 )
 
 
@@ -105,6 +106,9 @@ def load():
         "ssf_get_tiles": ([hp, vp], i32),
         "ssf_timing_read": ([hp, vp, vp], i32),
         "ssf_step": ([hp, vp, i64, dbl, i32, i64, vp], i32),
+        "ssf_step_noalloc": ([hp, vp, i64, dbl, i32, i64, vp], i32),
+        "ssf_noalloc_scratch_bytes": ([], i64),
+        "ssf_noalloc_scratch_need": ([hp], i64),
         "ssf_fft": ([hp, vp, i32, i32], i32),
         "ssf_observables": ([hp, vp, vp], i32),
         "ssf_obs_read": ([hp, vp, vp, i64], i32),

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -331,6 +332,10 @@ struct ssf_handle {
   long long part_cap = 0;
   double* dscal = nullptr;             // device scalars: [0] scale
   void* work = nullptr;                // field-sized workspace (lazy)
+  // Allocation-free steps (ssf_step_noalloc): while set, kinetic tables are
+  // built here for the call (up to two: dt and dt/2) instead of in the cache.
+  double2* ktfix = nullptr;
+  int ktfix_used = 0;
   // optional per-pass timing: an event pair around every pass launch
   int timing = 0;
   std::vector<hipEvent_t> ev[ssf::NUM_PASS_KINDS];
@@ -491,8 +496,30 @@ ssf_status check_field(const ssf_handle* h, const void* p, const char* what) {
   return SSF_OK;
 }
 
-// Kinetic tables for (dt, imag): built on the device once, then reused.
+// Kinetic factor tables of the three axes for (dt, imag) into t[nx | ny | nz].
+ssf_status build_ktab(ssf_handle* h, double2* t, double dt, int imag) {
+  const double inv_n = 1.0 / (double)h->npts;
+  for (int a = 0; a < 3; ++a) {
+    const int n = h->n[a];
+    const double kfac = TWO_PI / (h->hi[a] - h->lo[a]);
+    hipLaunchKernelGGL(ktab_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, h->stream, t, n, kfac, 0.5 * dt,
+                       imag, a == 2 ? inv_n : 1.0);
+    HIP_TRY(hipGetLastError());
+    t += n;
+  }
+  return SSF_OK;
+}
+
+// Kinetic tables for (dt, imag): built on the device once, then reused.  In
+// an allocation-free call they are built into the call's scratch instead.
 ssf_status get_ktab(ssf_handle* h, double dt, int imag, const double2** out) {
+  if (h->ktfix) {
+    if (h->ktfix_used >= 2) return fail(SSF_E_INVALID, "more than two kinetic tables in one allocation-free call");
+    double2* t = h->ktfix + (size_t)h->ktfix_used++ * (size_t)(h->n[0] + h->n[1] + h->n[2]);
+    SSF_TRY(build_ktab(h, t, dt, imag));
+    *out = t;
+    return SSF_OK;
+  }
   for (auto& k : h->kt)
     if (k.t && k.dt == dt && k.imag == imag) {
       k.use = ++h->kt_clock;
@@ -505,16 +532,7 @@ ssf_status get_ktab(ssf_handle* h, double dt, int imag, const double2** out) {
     if (k.use < slot->use) slot = &k;
   }
   if (!slot->t) HIP_TRY(hipMalloc(&slot->t, sizeof(double2) * (h->n[0] + h->n[1] + h->n[2])));
-  double2* t = slot->t;
-  const double inv_n = 1.0 / (double)h->npts;
-  for (int a = 0; a < 3; ++a) {
-    const int n = h->n[a];
-    const double kfac = TWO_PI / (h->hi[a] - h->lo[a]);
-    hipLaunchKernelGGL(ktab_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, h->stream, t, n, kfac, 0.5 * dt,
-                       imag, a == 2 ? inv_n : 1.0);
-    HIP_TRY(hipGetLastError());
-    t += n;
-  }
+  SSF_TRY(build_ktab(h, slot->t, dt, imag));
   slot->dt = dt;
   slot->imag = imag;
   slot->use = ++h->kt_clock;
@@ -964,8 +982,8 @@ static ssf_status run_steps_tvt(ssf_handle* h, void* psi, int64_t nsteps, double
   return SSF_OK;
 }
 
-ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time, int64_t obs_every,
-                    ssf_obs* obs_dev) {
+static ssf_status check_step_args(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time,
+                                  int64_t obs_every) {
   SSF_TRY(check_handle(h));
   SSF_TRY(check_field(h, psi, "psi"));
   if (nsteps < 0) return fail(SSF_E_INVALID, "nsteps must be >= 0");
@@ -973,12 +991,108 @@ ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t
   if (!std::isfinite(dt) || dt == 0.0) return fail(SSF_E_INVALID, "dt must be finite and nonzero");
   if (time == SSF_IMAG && dt < 0.0) return fail(SSF_E_INVALID, "imaginary time needs dt > 0");
   if (obs_every < 0) return fail(SSF_E_INVALID, "obs_every must be >= 0");
-  if (nsteps == 0) return SSF_OK;
-  if (h->split == SSF_SPLIT_TVT) {
-    if (time == SSF_IMAG) return fail(SSF_E_UNSUPPORTED, "imaginary time uses the V/2-T-V/2 ordering");
-    return run_steps_tvt(h, psi, nsteps, dt, obs_every, obs_dev);
-  }
+  if (time == SSF_IMAG && h->split == SSF_SPLIT_TVT)
+    return fail(SSF_E_UNSUPPORTED, "imaginary time uses the V/2-T-V/2 ordering");
+  return SSF_OK;
+}
+
+static ssf_status dispatch_steps(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time, int64_t obs_every,
+                                 ssf_obs* obs_dev) {
+  if (h->split == SSF_SPLIT_TVT) return run_steps_tvt(h, psi, nsteps, dt, obs_every, obs_dev);
   return run_steps(h, psi, psi, nsteps, dt, time == SSF_IMAG ? 1 : 0, obs_every, obs_dev, true);
+}
+
+ssf_status ssf_step(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time, int64_t obs_every,
+                    ssf_obs* obs_dev) {
+  SSF_TRY(check_step_args(h, psi, nsteps, dt, time, obs_every));
+  if (nsteps == 0) return SSF_OK;
+  return dispatch_steps(h, psi, nsteps, dt, time, obs_every, obs_dev);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free steps.  Everything a step sequence writes besides the field
+// and the observation records -- the kinetic tables of its dt (two for the
+// T/2-V-T/2 ordering), the FP64 partial sums of the reducing passes and the
+// device scale of imaginary time -- lives in one static device array per
+// device instead of in handle memory allocated on demand.  Host code never
+// uses the array's name as an address: its device address is looked up once
+// per device and kept in scratch_dev[].
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the device must be current).
+ssf_status scratch_address(int device, char** out) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return fail(SSF_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SSF_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    scratch_dev[device] = (char*)p;
+  }
+  *out = scratch_dev[device];
+  return SSF_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Scratch layout of one call: [device scalars | 2 kinetic tables | partials].
+size_t scratch_need(const ssf_handle* h, size_t* kt_off, size_t* part_off) {
+  *kt_off = 256;
+  *part_off = *kt_off + round256(2 * sizeof(double2) * (size_t)(h->n[0] + h->n[1] + h->n[2]));
+  return *part_off + sizeof(double) * ssf::NRED_OBS * (size_t)h->part_cap;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ssf_noalloc_scratch_bytes(void) { return (int64_t)SCRATCH_BYTES; }
+
+int64_t ssf_noalloc_scratch_need(ssf_handle* h) {
+  if (!h) return -1;
+  size_t a, b;
+  return (int64_t)scratch_need(h, &a, &b);
+}
+
+ssf_status ssf_step_noalloc(ssf_handle* h, void* psi, int64_t nsteps, double dt, int32_t time, int64_t obs_every,
+                            ssf_obs* obs_dev) {
+  SSF_TRY(check_step_args(h, psi, nsteps, dt, time, obs_every));
+  size_t kt_off, part_off;
+  const size_t need = scratch_need(h, &kt_off, &part_off);
+  if (need > SCRATCH_BYTES)
+    return fail(SSF_E_INVALID, "grid too large for the allocation-free step: it needs " + std::to_string(need) +
+                                   " bytes of scratch, the maximum is " + std::to_string(SCRATCH_BYTES));
+  char* base = nullptr;
+  SSF_TRY(scratch_address(h->device, &base));
+  if (nsteps == 0) return SSF_OK;
+  // point the handle's per-call buffers into the scratch for this call only;
+  // per-pass timing would create events, so it is off for the call
+  double* const saved_partials = h->partials;
+  double* const saved_dscal = h->dscal;
+  const int saved_timing = h->timing;
+  h->dscal = (double*)base;
+  h->ktfix = (double2*)(base + kt_off);
+  h->ktfix_used = 0;
+  h->partials = (double*)(base + part_off);
+  h->timing = 0;
+  const ssf_status st = dispatch_steps(h, psi, nsteps, dt, time, obs_every, obs_dev);
+  h->partials = saved_partials;
+  h->dscal = saved_dscal;
+  h->ktfix = nullptr;
+  h->ktfix_used = 0;
+  h->timing = saved_timing;
+  return st;
 }
 
 ssf_status ssf_observables(ssf_handle* h, const void* psi, ssf_obs* obs_dev) {
