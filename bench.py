@@ -60,7 +60,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point split-step updates/s + HBM GB/s vs roofline, c64 vs c128 at ≤1e-4 L2"
-ALL_SECTIONS = ("c128", "accuracy", "cpu", "batch", "adjoint", "c3", "tvt", "obs")
+ALL_SECTIONS = ("c128", "accuracy", "cpu", "batch", "adjoint", "c3", "tvt", "obs", "chip")
 ACCURACY_STEPS = 10000
 
 
@@ -190,14 +190,15 @@ def measured_traffic(kernel_kind, variant, grid_n, dtype):
 PASS_AXIS = {"x_fwd": 0, "x_inv": 0, "x_inv_phase_fwd": 0, "yz_fwd": 1, "yz_inv": 1, "z_fwd_kin_inv": 2}
 
 
-def roofline_entry(passes, grid, esize, tiles, storage):
+def roofline_entry(passes, grid, esize, tiles, storage, extra_bytes=None):
     """Roofline of the pass kind with the largest total time in `passes`
     ({kind: (ms, launches)}, HIP events around every launch): algorithmic
-    bytes per launch (one read and one write of the field) over the average
+    bytes per launch (one read and one write of the field, plus
+    extra_bytes[kind] per point for a table the pass reads) over the average
     launch duration, against the 8 TB/s HBM peak."""
     name, (tot_ms, n) = max(passes.items(), key=lambda kv: kv[1][0])
     avg_s = tot_ms * 1e-3 / max(n, 1)
-    bpl = 2.0 * esize * grid.points
+    bpl = (2.0 * esize + (extra_bytes or {}).get(name, 0)) * grid.points
     achieved = bpl / avg_s / 1e9
     var = tiles[PASS_AXIS[name]] if tiles else 0
     traffic = measured_traffic(name, var, grid.n, storage)
@@ -354,6 +355,125 @@ def section_batch(torch, ssf, device, steps=None, count=96, chunk=50, imag_steps
         "max_norm_drift": float(np.max(np.abs(norms - 1.0))),
         "accuracy_vs_c128": acc,
     }
+
+
+# ---------------------------------------------------------------------------
+# atom chip (Sec. III potential, Sec. V populations, Fig. 6 sweep)
+# ---------------------------------------------------------------------------
+def section_chip(torch, ssf, device, steps=2000, sweep_steps=1000, obs_every=100, chunk=50, imag_steps=2000,
+                 window=200):
+    import numpy as np
+    import synth
+    from paper_1309_2451_amd.states import chip_guide_state
+    cfg = synth.config_chip(i_mid=0.07)
+    g = cfg["grid"]
+    args = (cfg["paths"], cfg["currents"], cfg["b_bias"], cfg["b_ip"], cfg["length_unit"], cfg["mu_over_e0"],
+            cfg["omega_z"], cfg["z_c"])
+    nseg = sum(len(p) - 1 for p in cfg["paths"])
+    log("chip: potential on %s (%d wire segments), initial state" % (g.n, nseg))
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64", device=device)
+    V = s.chip_potential(*args)                            # warm-up (segment upload)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.chip_potential(*args, out=V)
+    e1.record()
+    torch.cuda.synchronize()
+    v_ms = e0.elapsed_time(e1)
+    psi0 = chip_guide_state(torch, cfg, device, steps=imag_steps)
+    s.set_potential_table(V)
+    s.set_partition_z(cfg["x_lo"], cfg["x_hi"])
+    ch, _ = s.tune(reps=5)
+    out = {"workload": "atom chip 256x64x1024 points over 20 x 8 x 1000 um, 6Li, I_L = I_R = 0.1 A, I_M = 0.07 A, "
+                       "B_b = 0.014 T, B_ip = 0.03 T, omega_z = 2 pi 5 Hz, dt = 1e-6 s, FP64 potential table, "
+                       "complex64 storage, observations every %d steps" % obs_every,
+           "potential_ms": v_ms, "segments": nseg, "tiles": ch}
+    # steady-state pass times, then the timed steps, complex64 and complex128
+    for dtype in ("c64", "c128"):
+        if dtype == "c128":
+            s.close()
+            s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
+            s.set_potential_table(V)
+            s.set_partition_z(cfg["x_lo"], cfg["x_hi"])
+            s.set_tiles(ch)
+        obs = s.obs_buffer(max(steps, window) // obs_every)
+        f = psi0.to(s.tdtype).contiguous().clone()
+        s.set_timing(True)
+        s.step(f, window, cfg["dt"], obs_every=obs_every, obs_buf=obs)
+        win = s.timing_read()
+        s.set_timing(False)
+        f = psi0.to(s.tdtype).contiguous().clone()
+        torch.cuda.synchronize()
+        e0.record()
+        s.step(f, steps, cfg["dt"], obs_every=obs_every, obs_buf=obs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rec = s.read_obs(obs, steps // obs_every)
+        r = {"value": g.points * steps / (ms * 1e-3), "ms_per_step": ms / steps, "steps": steps,
+             "pass_times": pass_summary(win), "final_populations": [float(v) for v in rec[-1]["pop"]],
+             "norm_drift": float(rec[-1]["norm"] - 1.0), "mean_z_final": float(rec[-1]["mean"][2])}
+        if dtype == "c64":
+            # populations (midline regions) and <z> against time, at most 50 samples
+            every = max(1, len(rec) // 50)
+            sub = rec[every - 1::every]
+            r["t_s"] = [float(v) * 1e-6 for v in sub["step"]]
+            r["pops"] = [[float(q) for q in v] for v in sub["pop"]]
+            r["mean_z"] = [float(v[2]) for v in sub["mean"]]
+        if dtype == "c64":
+            esize = 8
+            # the x passes also read the FP64 potential table once per point
+            r["roofline"] = roofline_entry(win, g, esize, ch, "c64",
+                                           extra_bytes={"x_inv_phase_fwd": 8, "x_fwd": 8, "x_inv": 8})
+            psi64 = f
+        else:
+            r["c64_vs_c128_rel_l2"] = rel_l2(torch, psi64, f)
+        out[dtype] = r
+    s.close()
+    del V
+    torch.cuda.empty_cache()
+    # the Fig. 6 sweep: middle-wire currents x (counter-intuitive, intuitive), one batch
+    cur = synth.chip_sweep_currents()
+    cfgs = [synth.config_chip(i_mid=c, intuitive=iv) for iv in (False, True) for c in cur]
+    log("chip sweep: %d instances, potentials and initial states" % len(cfgs))
+    tabs, fields = [], []
+    for c in cfgs:
+        h = ssf.Solver(g.n, g.lo, g.hi, "c64", device=device)
+        tabs.append(h.chip_potential(c["paths"], c["currents"], c["b_bias"], c["b_ip"], c["length_unit"],
+                                     c["mu_over_e0"], c["omega_z"], c["z_c"]))
+        torch.cuda.synchronize()
+        h.close()
+        fields.append(chip_guide_state(torch, c, device, steps=imag_steps).to(torch.complex64).contiguous())
+    # final populations over the straight ends of the wires: midlines at -/+ 3.5 um
+    b = ssf.Batch([(g.n, g.lo, g.hi)] * len(cfgs), None, [-3.5] * len(cfgs), [3.5] * len(cfgs), dtype="c64",
+                  tables=tabs)
+    b.tune(reps=3)
+    warm = [f.clone() for f in fields]
+    b.run(warm, 2 * chunk, cfg["dt"], chunk=chunk)
+    del warm
+    obs = b.obs_buffer()
+    torch.cuda.synchronize()
+    log("chip sweep: timed run, %d steps" % sweep_steps)
+    e0.record()
+    b.run(fields, sweep_steps, cfg["dt"], chunk=chunk, obs_buf=obs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rec = b.read_obs(obs)
+    b.close()
+    n = len(cur)
+    out["sweep"] = {
+        "instances": len(cfgs), "steps": sweep_steps, "full_run_steps": cfg["steps"],
+        "value": len(cfgs) * g.points * sweep_steps / (ms * 1e-3), "unit": "updates/s", "ms": ms,
+        "i_mid": cur,
+        "p3_counter_intuitive": [float(r["pop"][2]) for r in rec[:n]],
+        "p3_intuitive": [float(r["pop"][2]) for r in rec[n:]],
+        "mean_z": [float(r["mean"][2]) for r in rec],
+        "max_norm_drift": float(np.max(np.abs(np.array([r["norm"] for r in rec]) - 1.0))),
+        "time_s": sweep_steps * 1e-6,
+    }
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -558,6 +678,9 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=None)
     ap.add_argument("--tvt-steps", type=int, default=1000)
     ap.add_argument("--obs-steps", type=int, default=10000)
+    ap.add_argument("--chip-steps", type=int, default=2000)
+    ap.add_argument("--chip-sweep-steps", type=int, default=1000,
+                    help="steps of the atom-chip current sweep (the full run is 10^5)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="record the plain field copy launches (2 x field bytes each) for calibrating "
                          "profiler byte counters")
@@ -722,6 +845,9 @@ def main():
         torch.cuda.empty_cache()
     if "c3" in sections:
         out["c3"] = section_c3(torch, ssf, device, steps=a.c3_steps)
+        torch.cuda.empty_cache()
+    if "chip" in sections:
+        out["chip"] = section_chip(torch, ssf, device, steps=a.chip_steps, sweep_steps=a.chip_sweep_steps)
         torch.cuda.empty_cache()
     if "cpu" in sections:
         log("CPU oracle baseline")

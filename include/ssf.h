@@ -114,6 +114,39 @@ ssf_status ssf_set_potential_table(ssf_handle* h, const void* v_dev, int32_t v_i
 /* Build the three-guide potential tables on the device (synchronous upload).
  * Errors: INVALID (nguides outside 1..3, sigma <= 0, null xc). */
 ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d);
+/* Atom-chip potential (Sec. III): thin wires on the chip surface y = 0, each a
+ * polyline in the (x, z) plane carrying a constant current; a homogeneous bias
+ * field b_bias along +x (across the wires) and an offset field b_ip along +z
+ * (along them); a harmonic trap of frequency omega_z along z centred at z_c.
+ * The field B is the Biot-Savart sum over the wires' straight segments (each
+ * by the closed-form finite-wire law) plus (b_bias, 0, b_ip), and
+ *     V = mu_over_e0 (|B| - b_ip) + omega_z^2 (z - z_c)^2 / 2
+ * (a low-field-seeking atom's magnetic energy measured from its value at the
+ * offset field).  Grid coordinates are in length units of length_unit
+ * metres; fields in tesla, currents in ampere; mu_over_e0 is the magnetic
+ * moment over the energy unit (per tesla), omega_z in inverse time units.
+ * Points on a segment's line get no contribution from it (keep the grid off
+ * the plane y = 0). */
+#define SSF_CHIP_MAX_WIRES 16
+typedef struct ssf_chip_desc {
+  int32_t nwires;          /* 1..16 */
+  const int32_t* npts;     /* host, points of each wire's polyline (>= 2) */
+  const double* path;      /* host, the (x, z) points of every wire, concatenated, length units */
+  const double* current;   /* host, current of each wire (A), from its first point to its last */
+  double b_bias;           /* T, along +x */
+  double b_ip;             /* T, along +z, >= 0 */
+  double length_unit;      /* metres per length unit */
+  double mu_over_e0;       /* magnetic moment / energy unit, per tesla */
+  double omega_z;          /* longitudinal trap frequency */
+  double z_c;              /* trap centre (length units) */
+} ssf_chip_desc;
+/* Evaluate the atom-chip potential on the handle's grid into V_dev, a
+ * caller-owned FP64 device table (Nz, Ny, Nx), in FP64 on the device; use it
+ * with ssf_set_potential_table(h, V_dev, 1) or a table batch.  Copies the
+ * segment list to a device buffer the handle keeps (synchronises the stream
+ * first; allocates when the list grows); the evaluation itself is enqueued.
+ * Errors: INVALID (null, misaligned, counts, non-finite values). */
+ssf_status ssf_chip_potential(ssf_handle* h, const ssf_chip_desc* d, double* V_dev);
 /* Remove the potential (free particle). */
 ssf_status ssf_clear_potential(ssf_handle* h);
 /* Guide regions for the populations: P1 counts grid points with x < x_lo,
@@ -264,6 +297,12 @@ typedef struct ssf_batch ssf_batch;
 ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf_ctap_desc* guides,
                             const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
                             ssf_batch** out);
+/* The same with borrowed potential tables instead of guides: vtabs[i] is a
+ * device FP64 table (Nz_i, Ny_i, Nx_i) of instance i (e.g. from
+ * ssf_chip_potential), kept alive by the caller while the batch runs. */
+ssf_status ssf_batch_create_tables(int32_t count, const ssf_grid_desc* grids, const double* const* vtabs,
+                                   const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
+                                   ssf_batch** out);
 ssf_status ssf_batch_run(ssf_batch* b, void* const* psi, int64_t nsteps, double dt, int64_t chunk,
                          ssf_obs* obs_dev);
 ssf_status ssf_batch_tune(ssf_batch* b, int32_t reps);

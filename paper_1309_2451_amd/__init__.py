@@ -144,6 +144,37 @@ class Solver:
         _ssf.call("ssf_set_potential_ctap", self.h, ctypes.byref(d))
         self.nguides = d.nguides
 
+    def chip_potential(self, paths, currents, b_bias, b_ip, length_unit, mu_over_e0, omega_z, z_c, out=None):
+        """The atom-chip potential (ssf_chip_potential) on this grid as a
+        float64 (Nz, Ny, Nx) tensor on the device (into `out` if given):
+        wires along the polylines `paths` (each (k, 2): x, z in length
+        units, on the chip surface y = 0) with `currents` (A), bias field
+        b_bias along x and offset field b_ip along z (T), length unit in
+        metres, moment over energy unit (per T), longitudinal trap omega_z
+        centred at z_c.  Use with set_potential_table."""
+        torch = self.torch
+        paths = [np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 2) for q in paths]
+        npts = np.ascontiguousarray([q.shape[0] for q in paths], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([q.ravel() for q in paths]))
+        cur = np.ascontiguousarray(currents, dtype=np.float64)
+        if cur.shape != (len(paths),):
+            raise ValueError("one current per wire")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        elif out.dtype != torch.float64 or tuple(out.shape) != self.shape or not out.is_contiguous() \
+                or out.device != self.device:
+            raise ValueError("out must be a contiguous float64 tensor of shape %s on %s" % (self.shape, self.device))
+        d = _ssf.ssf_chip_desc()
+        d.nwires = len(paths)
+        d.npts = npts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.path = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.current = cur.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.b_bias, d.b_ip, d.length_unit = float(b_bias), float(b_ip), float(length_unit)
+        d.mu_over_e0, d.omega_z, d.z_c = float(mu_over_e0), float(omega_z), float(z_c)
+        self._sync_stream()
+        _ssf.call("ssf_chip_potential", self.h, ctypes.byref(d), ctypes.c_void_p(out.data_ptr()))
+        return out
+
     def clear_potential(self):
         _ssf.call("ssf_clear_potential", self.h)
 
@@ -306,17 +337,22 @@ class Solver:
 
 class Batch:
     """Many independent instances (an ssf_batch): instance i has its own grid
-    n[i], lo[i], hi[i], guides (v0[i], sigma[i], xc[i] of shape (3, Nz_i)) and
-    partition (x_lo[i], x_hi[i]).  Instances with equal grids share tables and
-    are stepped together by one persistent launch per pass; the groups run
+    n[i], lo[i], hi[i], potential and partition (x_lo[i], x_hi[i]).  The
+    potential is either guides (v0[i], sigma[i], xc[i] of shape (3, Nz_i)) or,
+    with tables=..., a float64 device tensor (Nz_i, Ny_i, Nx_i) per instance
+    (borrowed: kept referenced here).  Instances with equal grids share tables
+    and are stepped together by one persistent launch per pass; the groups run
     concurrently.  Fields are a list of tensors (Nz_i, Ny_i, Nx_i)."""
 
-    def __init__(self, grids, guides, x_lo, x_hi, dtype="c64", device=None):
+    def __init__(self, grids, guides, x_lo, x_hi, dtype="c64", device=None, tables=None):
         torch = _torch()
         self.torch = torch
         self.count = len(grids)
-        if not (len(guides) == len(x_lo) == len(x_hi) == self.count) or self.count < 1:
-            raise ValueError("grids, guides, x_lo, x_hi must have one entry per instance")
+        if (guides is None) == (tables is None):
+            raise ValueError("give either guides or tables")
+        if not (len(guides if tables is None else tables) == len(x_lo) == len(x_hi) == self.count) \
+                or self.count < 1:
+            raise ValueError("grids, guides or tables, x_lo, x_hi must have one entry per instance")
         self.dtype = {"c64": SSF_C64, "c128": SSF_C128}[dtype]
         self.tdtype = torch.complex64 if self.dtype == SSF_C64 else torch.complex128
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -324,9 +360,22 @@ class Batch:
         cd = (_ssf.ssf_ctap_desc * self.count)()
         self._xc = []
         self.shapes = []
-        for i, ((n, lo, hi), (v0, sigma, xc)) in enumerate(zip(grids, guides)):
+        for i, (n, lo, hi) in enumerate(grids):
             for a in range(3):
                 gd[i].n[a], gd[i].lo[a], gd[i].hi[a] = int(n[a]), float(lo[a]), float(hi[a])
+            self.shapes.append((int(n[2]), int(n[1]), int(n[0])))
+        self._tables = None
+        if tables is not None:
+            tp = (ctypes.c_void_p * self.count)()
+            for i, t in enumerate(tables):
+                if t.dtype != torch.float64 or tuple(t.shape) != self.shapes[i] or not t.is_contiguous() \
+                        or t.device != self.device:
+                    raise ValueError("table %d must be a contiguous float64 tensor of shape %s on %s"
+                                     % (i, self.shapes[i], self.device))
+                tp[i] = t.data_ptr()
+            self._tables = list(tables)
+        for i, ((n, lo, hi), gdesc) in enumerate(zip(grids, guides if guides is not None else [])):
+            v0, sigma, xc = gdesc
             xc = np.ascontiguousarray(xc, dtype=np.float64)
             if xc.ndim != 2 or xc.shape[1] != int(n[2]) or not 1 <= xc.shape[0] <= 3:
                 raise ValueError("instance %d: xc must be (nguides, Nz)" % i)
@@ -336,15 +385,18 @@ class Batch:
                 cd[i].sigma[g] = float(sigma[g])
             cd[i].xc = xc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             self._xc.append(xc)
-            self.shapes.append((int(n[2]), int(n[1]), int(n[0])))
         lo_a = np.ascontiguousarray(x_lo, dtype=np.float64)
         hi_a = np.ascontiguousarray(x_hi, dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            _ssf.call("ssf_batch_create", self.count, gd, cd, lo_a.ctypes.data_as(dp), hi_a.ctypes.data_as(dp),
-                      self.dtype, ctypes.c_void_p(stream), ctypes.byref(h))
+            if tables is None:
+                _ssf.call("ssf_batch_create", self.count, gd, cd, lo_a.ctypes.data_as(dp), hi_a.ctypes.data_as(dp),
+                          self.dtype, ctypes.c_void_p(stream), ctypes.byref(h))
+            else:
+                _ssf.call("ssf_batch_create_tables", self.count, gd, tp, lo_a.ctypes.data_as(dp),
+                          hi_a.ctypes.data_as(dp), self.dtype, ctypes.c_void_p(stream), ctypes.byref(h))
         self.h = h
         self._ptrs = (ctypes.c_void_p * self.count)()
 

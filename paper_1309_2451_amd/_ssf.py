@@ -39,6 +39,7 @@ EXPORTS = (
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
     "ssf_batch_info", "ssf_batch_set_stream", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_bspline_eval", "ssf_status_string", "ssf_last_error",
     "ssf_step_noalloc", "ssf_noalloc_scratch_bytes", "ssf_noalloc_scratch_need",
+    "ssf_chip_potential", "ssf_batch_create_tables",
 )
 
 
@@ -49,6 +50,13 @@ class ssf_grid_desc(ctypes.Structure):
 class ssf_ctap_desc(ctypes.Structure):
     _fields_ = [("nguides", ctypes.c_int32), ("v0", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double * 3), ("xc", ctypes.POINTER(ctypes.c_double))]
+
+
+class ssf_chip_desc(ctypes.Structure):
+    _fields_ = [("nwires", ctypes.c_int32), ("npts", ctypes.POINTER(ctypes.c_int32)),
+                ("path", ctypes.POINTER(ctypes.c_double)), ("current", ctypes.POINTER(ctypes.c_double)),
+                ("b_bias", ctypes.c_double), ("b_ip", ctypes.c_double), ("length_unit", ctypes.c_double),
+                ("mu_over_e0", ctypes.c_double), ("omega_z", ctypes.c_double), ("z_c", ctypes.c_double)]
 
 
 class ssf_obs(ctypes.Structure):
@@ -122,6 +130,8 @@ def load():
         "ssf_profile_grad": ([hp, vp, i32, vp, i32, vp], i32),
         "ssf_batch_create": ([i32, vp, vp, dp, dp, i32, vp, ctypes.POINTER(hp)], i32),
         "ssf_batch_run": ([hp, vp, i64, dbl, i64, vp], i32),
+        "ssf_batch_create_tables": ([i32, vp, vp, dp, dp, i32, vp, ctypes.POINTER(hp)], i32),
+        "ssf_chip_potential": ([hp, ctypes.POINTER(ssf_chip_desc), vp], i32),
         "ssf_batch_tune": ([hp, i32], i32),
         "ssf_batch_info": ([hp, ctypes.POINTER(i32), vp], i32),
         "ssf_batch_set_stream": ([hp, vp], i32),

@@ -31,12 +31,14 @@ enum PassKind : int {
   NUM_PASS_KINDS = 6
 };
 
-// One instance of a batched launch: its field and its guide tables
-// (A | D | B, MAX_GUIDES planes each, as for a single handle).
+// One instance of a batched launch: its field and its potential -- guide
+// tables (A | D | B, MAX_GUIDES planes each, as for a single handle) or an
+// FP64 (nz, ny, nx) table.
 struct InstDesc {
   const void* in;
   void* out;
   const double* ctap;
+  const double* vtab;
   int ix_lo, ix_hi;        // guide partition of this instance (observations)
 };
 

@@ -634,7 +634,7 @@ __device__ __forceinline__ unsigned elem_off(unsigned off, int n, const PassArgs
 // sA = A_g(x, z) for g < MAX_GUIDES, x < N and sB = B_g(y), both in LDS.
 // Tables: read from global memory.
 template <class G, int r>
-__device__ __forceinline__ void potentials(const PassArgs& a, const double* sA, const double* sB,
+__device__ __forceinline__ void potentials(const PassArgs& a, const double* sA, const double* sB, const void* vtab,
                                            const Pen<G, r>& p, double (&V)[G::E]) {
   constexpr int N = G::NN, U = Pen<G, r>::U;
   if (a.vkind == V_CTAP) {
@@ -649,13 +649,13 @@ __device__ __forceinline__ void potentials(const PassArgs& a, const double* sA, 
       }
     }
   } else if (a.vkind == V_TAB64) {
-    const double* __restrict__ T = (const double*)a.vtab;
+    const double* __restrict__ T = (const double*)vtab;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int m = 0; m < r; ++m) V[u * r + m] = T[p.off[u] + p.i[u] + m * (N / r)];
   } else if (a.vkind == V_TAB32) {
-    const float* __restrict__ T = (const float*)a.vtab;
+    const float* __restrict__ T = (const float*)vtab;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -716,7 +716,12 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 
 // is transformed the only vector-memory reads in flight are the prefetch of
 // the next tile's values (and of its per-pencil kinetic factors), which
 // therefore overlap the arithmetic.
-template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH>
+//
+// VT (with LEAN, fused x pass): the potential comes from an FP64 table in
+// global memory; each tile's values at the mid-op positions are prefetched
+// with the tile, so the table read overlaps the arithmetic like the field's.
+template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH,
+          bool VT = false>
 __global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM))
 pass_kernel(PassArgs a) {
   using G = PassGeom<S, N, PX, PO, CONTIG, EM>;
@@ -758,6 +763,8 @@ pass_kernel(PassArgs a) {
   const InstDesc SSF_CONST* idesc = (const InstDesc SSF_CONST*)a.inst;
   const S* in_k = (const S*)a.in;                                  // field read by load_tile
   S* out_k = (S*)a.out;                                            // field written by the tile loop
+  const void* vt_in = a.vtab;                                      // potential table of the prefetched tile
+  const void* vt_k = a.vtab;                                       // potential table of the current tile
   int k_in = -1, k_out = -1;
   // tables into LDS (once per workgroup; the guide B table again when the instance changes)
   for (int j = threadIdx.x; j < N; j += WG) {
@@ -773,12 +780,14 @@ pass_kernel(PassArgs a) {
   // workgroup size is a multiple of P), so the z pass needs one per-pencil
   // kinetic factor kx(x) ky(y) per thread and tile.
   S raw[E];
+  double vraw[VT ? E : 1];                                         // VT: potential at the mid-op positions
   double2 kx_n, ky_n;
   auto load_tile = [&](int tg) {
     const int k = BATCH ? __builtin_amdgcn_readfirstlane(tg / tpi) : 0;
     const int t = tg - k * tpi;
     if (BATCH && k != k_in) {
       in_k = (const S*)idesc[k].in;
+      if constexpr (VT) vt_in = idesc[k].vtab;
       k_in = k;
     }
     const S* __restrict__ in = in_k;
@@ -795,6 +804,15 @@ pass_kernel(PassArgs a) {
       kx_n = a.kt[0][p.c0[0]];
       ky_n = a.kt[1][p.c1[0]];
     }
+    if constexpr (VT) {
+      Pen<G, rm> pm;
+      pencils(pm, a, t);
+      const double* T = (const double*)vt_in;
+#pragma unroll
+      for (int u = 0; u < UM; ++u)
+#pragma unroll
+        for (int m = 0; m < rm; ++m) vraw[u * rm + m] = ldg(T + pm.off[u] + pm.i[u] + m * (N / rm));
+    }
   };
   // the adjoint and global potential tables read global memory inside the
   // tile, so those passes load each tile when they reach it
@@ -809,6 +827,7 @@ pass_kernel(PassArgs a) {
     const int t1 = t / a.tiles_x;
     if (BATCH && k != k_out) {
       out_k = (S*)idesc[k].out;
+      vt_k = idesc[k].vtab;
       k_out = k;
     }
     S* __restrict__ out = out_k;
@@ -835,6 +854,11 @@ pass_kernel(PassArgs a) {
     for (int e = 0; e < E; ++e) v[e] = make_double2((double)raw[e].x, (double)raw[e].y);
     double2 kxy = make_double2(1.0, 0.0);
     if constexpr (KZ) kxy = cmul(kx_n, ky_n);
+    double vcur[VT ? E : 1];
+    if constexpr (VT) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) vcur[e] = vraw[e];
+    }
     if (prefetch && tg + tstep < tend) load_tile(tg + tstep);
 
     double acc[NRED_OBS];
@@ -853,7 +877,7 @@ pass_kernel(PassArgs a) {
         }
         if (a.pre & PRE_VPHASE) {
           double V[E];
-          potentials<G, r0>(a, s_A, s_dyn, p, V);
+          potentials<G, r0>(a, s_A, s_dyn, vt_k, p, V);
 #pragma unroll
           for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpre, a.imag));
         }
@@ -869,7 +893,11 @@ pass_kernel(PassArgs a) {
           Pen<G, rm> p;
           pencils(p, a, t);
           double V[E];
-          if constexpr (LEAN) {
+          if constexpr (LEAN && VT) {
+            // table potential, prefetched with the tile
+#pragma unroll
+            for (int e = 0; e < E; ++e) V[e] = vcur[e];
+          } else if constexpr (LEAN) {
             // guide potential from LDS (the host selects LEAN only for it or for V = 0)
 #pragma unroll
             for (int u = 0; u < UM; ++u) {
@@ -881,6 +909,8 @@ pass_kernel(PassArgs a) {
                 V[u * rm + m] = ctap ? -(s_A[x] * b0 + s_A[N + x] * b1 + s_A[2 * N + x] * b2) : 0.0;
               }
             }
+          }
+          if constexpr (LEAN) {
             if (a.small_phase == 2) {
 #pragma unroll
               for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_tiny<LOWP>(V[e] * a.cmid));
@@ -894,7 +924,7 @@ pass_kernel(PassArgs a) {
           } else if (a.mid == MID_VNORM) {
             // end of one step (half-step factor), the norm of that step's
             // field (FP64, ragged rows weighted zero), start of the next
-            potentials<G, rm>(a, s_A, s_dyn, p, V);
+            potentials<G, rm>(a, s_A, s_dyn, vt_k, p, V);
 #pragma unroll
             for (int u = 0; u < UM; ++u) {
               const double w = p.ok[u] ? 1.0 : 0.0;
@@ -908,7 +938,7 @@ pass_kernel(PassArgs a) {
               }
             }
           } else {
-            potentials<G, rm>(a, s_A, s_dyn, p, V);
+            potentials<G, rm>(a, s_A, s_dyn, vt_k, p, V);
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cmid, a.imag));
           }
@@ -935,7 +965,7 @@ pass_kernel(PassArgs a) {
       if constexpr (LEAN) {
       } else if constexpr (CONTIG) {
         double V[E];
-        if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, p, V);
+        if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, vt_k, p, V);
         if (a.post & POST_VPHASE) {
 #pragma unroll
           for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpost, a.imag));
@@ -1085,7 +1115,8 @@ hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t s
 }
 
 // The lean x kernel serves the fused x pass of the steady-state steps (only
-// the potential phase, guide potential or none, real time); lean y/z kernels
+// the potential phase, real time): guide potential or none, or (VT) an FP64
+// potential table read with the tile; lean y/z kernels
 // serve every strided pass without a reduction.  Batched launches (B) exist
 // for the passes of a real-time step: x forward with a pre phase, x inverse
 // with a post phase, the lean fused x pass and the lean y/z passes.
@@ -1094,8 +1125,9 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
   constexpr int CR = Shape<N>::cr();
   constexpr int WGC = PassGeom<S, N, CR, 1, true, 1>::WG;
   const size_t dync = sizeof(double) * MAX_GUIDES * (size_t)a.ny;
-  static OccCache occ[4];
+  static OccCache occ[5];
   const bool lean_x = a.pre == 0 && a.post == 0 && !a.imag && (a.vkind == V_CTAP || a.vkind == V_NONE);
+  const bool lean_t = a.pre == 0 && a.post == 0 && !a.imag && a.vkind == V_TAB64 && a.mid == MID_VPHASE;
   switch (kind) {
     case CONTIG_FWD:
       return launch_persistent(pass_kernel<S, N, CR, 1, true, false, false, 1, false, B>, WGC, dync, a, tiles, st,
@@ -1107,6 +1139,9 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
       if (lean_x)
         return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B>, WGC, dync, a, tiles, st,
                                  occ[2]);
+      if (lean_t)
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B, true>, WGC, dync, a, tiles,
+                                 st, occ[4]);
       if constexpr (B) return hipErrorInvalidValue;
       else
         return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false, false>, WGC, dync, a, tiles, st,

@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) obs_reduce_batch(PassArgs a, int rows) {
   const long long pl = (long long)a.nz * a.nx;
   const long long gplane = (long long)ssf::MAX_GUIDES * pl;
   const double* A = d.ctap;
-  const double* B = d.ctap + 2 * gplane;
+  const double* B = d.ctap ? d.ctap + 2 * gplane : nullptr;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int e = threadIdx.x; e < rows * a.nx; e += 256) {
     const int y = y0 + e / a.nx, x = e % a.nx;
@@ -230,7 +230,8 @@ __global__ void __launch_bounds__(256) obs_reduce_batch(PassArgs a, int rows) {
     const double2 v = ssf::ld2(in + ((long long)z * a.ny + y) * a.nx + x);
     const double rho = v.x * v.x + v.y * v.y;
     const long long o = (long long)z * a.nx + x;
-    const double V = -(A[o] * B[y] + A[pl + o] * B[a.ny + y] + A[2 * pl + o] * B[2 * a.ny + y]);
+    const double V = d.vtab ? d.vtab[((long long)z * a.ny + y) * a.nx + x]
+                            : -(A[o] * B[y] + A[pl + o] * B[a.ny + y] + A[2 * pl + o] * B[2 * a.ny + y]);
     acc[0] += rho;
     acc[1] += (a.lo[0] + x * a.d[0]) * rho;
     acc[2] += (a.lo[1] + y * a.d[1]) * rho;
@@ -291,6 +292,77 @@ __global__ void __launch_bounds__(256) density_xz_kernel(const S* in, int nx, in
 }
 
 // ---------------------------------------------------------------------------
+// Atom-chip potential (Sec. III): thin current-carrying wires lying in the
+// chip plane y = 0, a homogeneous bias field across them (x) and an offset
+// field along them (z), plus a harmonic trap along z.  One thread per grid
+// point sums the Biot-Savart field of every straight wire segment; the
+// segments are staged through LDS in chunks.
+// ---------------------------------------------------------------------------
+struct ChipSeg {
+  double ax, az;    // segment start (x, z), length units
+  double lx, lz;    // segment vector end - start
+  double kI;        // mu0 I / (4 pi length_unit): tesla times length units
+  double pad;
+};
+constexpr int CHIP_CHUNK = 1024;   // segments per LDS stage (48 KiB)
+
+// Field of one straight segment at P = (px, py, pz) relative to the segment
+// start (a = P - A) and end (b = P - B, B = A + L): the finite-wire law
+//   dB = k I (L x a) (L.a/|a| - L.b/|b|) / |L x a|^2,
+// which reduces to mu0 I / (2 pi rho) for an infinitely long wire.  With the
+// wire in the plane y = 0, L = (lx, 0, lz) and L x a = (-lz py, lz ax - lx az,
+// lx py).  A point on the segment's line gets nothing from it.
+__device__ __forceinline__ void seg_field(const ChipSeg& s, double px, double py, double pz, double& bx,
+                                          double& by, double& bz) {
+  const double ax = px - s.ax, az = pz - s.az;
+  const double cy = s.lz * ax - s.lx * az;
+  const double l2 = s.lx * s.lx + s.lz * s.lz;
+  const double c2 = py * py * l2 + cy * cy;
+  if (c2 == 0.0) return;
+  const double la = s.lx * ax + s.lz * az;       // L.a
+  const double lb = la - l2;                       // L.b
+  const double bxr = ax - s.lx, bzr = az - s.lz;
+  const double ra = sqrt(ax * ax + py * py + az * az);
+  const double rb = sqrt(bxr * bxr + py * py + bzr * bzr);
+  const double f = s.kI * (la / ra - lb / rb) / c2;
+  bx -= f * s.lz * py;
+  by += f * cy;
+  bz += f * s.lx * py;
+}
+
+// V[z][y][x] = mu_e (|B| - b_ip) + omega_z^2 (z - z_c)^2 / 2, B = wires +
+// (b_bias, 0, b_ip).  |B| - b_ip is formed as (|B|^2 - b_ip^2) / (|B| + b_ip)
+// with |B|^2 - b_ip^2 = Bx^2 + By^2 + Bwz (Bwz + 2 b_ip): at the guide centres
+// |B| is close to b_ip, and the direct difference would cancel.
+__global__ void __launch_bounds__(256) chip_kernel(double* V, int nx, int ny, int nz, double lox, double loy,
+                                                   double loz, double dx, double dy, double dz, const ChipSeg* seg,
+                                                   int nseg, double b_bias, double b_ip, double mu_e, double omz,
+                                                   double z_c) {
+  __shared__ ChipSeg s_seg[CHIP_CHUNK];
+  const long long npts = (long long)nx * ny * nz;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int x = (int)(i % nx);
+  const int y = (int)((i / nx) % ny);
+  const int z = (int)(i / ((long long)nx * ny));
+  const double px = lox + x * dx, py = loy + y * dy, pz = loz + z * dz;
+  double bx = 0.0, by = 0.0, bz = 0.0;
+  for (int c0 = 0; c0 < nseg; c0 += CHIP_CHUNK) {
+    const int cn = min(CHIP_CHUNK, nseg - c0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < cn; j += 256) s_seg[j] = seg[c0 + j];
+    __syncthreads();
+    if (i < npts)
+      for (int j = 0; j < cn; ++j) seg_field(s_seg[j], px, py, pz, bx, by, bz);
+  }
+  if (i >= npts) return;
+  const double tx = bx + b_bias, tz = bz + b_ip;
+  const double mag = sqrt(tx * tx + by * by + tz * tz);
+  const double excess = (tx * tx + by * by + bz * (bz + 2.0 * b_ip)) / (mag + b_ip);
+  const double w = pz - z_c;
+  V[i] = mu_e * excess + 0.5 * omz * omz * w * w;
+}
+
+// ---------------------------------------------------------------------------
 // Handle.
 // ---------------------------------------------------------------------------
 struct KTab {
@@ -336,6 +408,8 @@ struct ssf_handle {
   // built here for the call (up to two: dt and dt/2) instead of in the cache.
   double2* ktfix = nullptr;
   int ktfix_used = 0;
+  ChipSeg* chipseg = nullptr;          // wire segments of ssf_chip_potential (device, grows)
+  size_t chipseg_cap = 0;
   // optional per-pass timing: an event pair around every pass launch
   int timing = 0;
   std::vector<hipEvent_t> ev[ssf::NUM_PASS_KINDS];
@@ -683,6 +757,7 @@ ssf_status ssf_destroy(ssf_handle* h) {
   if (h->partials) (void)hipFree(h->partials);
   if (h->dscal) (void)hipFree(h->dscal);
   if (h->work) (void)hipFree(h->work);
+  if (h->chipseg) (void)hipFree(h->chipseg);
   for (auto& pool : h->ev)
     for (hipEvent_t ev : pool) (void)hipEventDestroy(ev);
   delete h;
@@ -834,6 +909,58 @@ ssf_status ssf_set_potential_ctap(ssf_handle* h, const ssf_ctap_desc* d) {
   h->vmax = vmax;
   h->vkind = ssf::V_CTAP;
   h->vtab = nullptr;
+  return SSF_OK;
+}
+
+ssf_status ssf_chip_potential(ssf_handle* h, const ssf_chip_desc* d, double* V_dev) {
+  SSF_TRY(check_handle(h));
+  if (!d || !V_dev) return fail(SSF_E_INVALID, "null chip description or output");
+  if (((uintptr_t)V_dev) % sizeof(double) != 0) return fail(SSF_E_INVALID, "V_dev is not aligned to 8 bytes");
+  if (d->nwires < 1 || d->nwires > SSF_CHIP_MAX_WIRES || !d->npts || !d->path || !d->current)
+    return fail(SSF_E_INVALID, "chip needs 1..16 wires with point counts, paths and currents");
+  if (!(d->length_unit > 0.0) || !std::isfinite(d->length_unit))
+    return fail(SSF_E_INVALID, "length_unit must be positive");
+  if (!std::isfinite(d->b_bias) || !std::isfinite(d->b_ip) || !(d->b_ip >= 0.0) || !std::isfinite(d->mu_over_e0) ||
+      !std::isfinite(d->omega_z) || !std::isfinite(d->z_c))
+    return fail(SSF_E_INVALID, "chip fields, moment and trap must be finite (b_ip >= 0)");
+  // straight segments between consecutive points of every wire
+  std::vector<ChipSeg> seg;
+  const double k0 = 1.25663706212e-6 / (4.0 * 3.14159265358979323846) / d->length_unit;
+  long long off = 0;
+  for (int w = 0; w < d->nwires; ++w) {
+    const int np = d->npts[w];
+    if (np < 2) return fail(SSF_E_INVALID, "every wire needs at least 2 points");
+    if (!std::isfinite(d->current[w])) return fail(SSF_E_INVALID, "currents must be finite");
+    for (int q = 0; q + 1 < np; ++q) {
+      const double* A = d->path + 2 * (off + q);
+      ChipSeg c;
+      c.ax = A[0];
+      c.az = A[1];
+      c.lx = A[2] - A[0];
+      c.lz = A[3] - A[1];
+      c.kI = k0 * d->current[w];
+      c.pad = 0.0;
+      if (!std::isfinite(c.ax) || !std::isfinite(c.az) || !std::isfinite(c.lx) || !std::isfinite(c.lz))
+        return fail(SSF_E_INVALID, "wire points must be finite");
+      seg.push_back(c);
+    }
+    off += np;
+  }
+  if (seg.size() > h->chipseg_cap) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->chipseg) (void)hipFree(h->chipseg);
+    h->chipseg = nullptr;
+    h->chipseg_cap = 0;
+    HIP_TRY(hipMalloc(&h->chipseg, sizeof(ChipSeg) * seg.size()));
+    h->chipseg_cap = seg.size();
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(h->chipseg, seg.data(), sizeof(ChipSeg) * seg.size(), hipMemcpyHostToDevice));
+  const long long blocks = ceil_div(h->npts, 256);
+  hipLaunchKernelGGL(chip_kernel, dim3((unsigned)blocks), dim3(256), 0, h->stream, V_dev, h->n[0], h->n[1], h->n[2],
+                     h->lo[0], h->lo[1], h->lo[2], h->d[0], h->d[1], h->d[2], h->chipseg, (int)seg.size(), d->b_bias,
+                     d->b_ip, d->mu_over_e0, d->omega_z, d->z_c);
+  HIP_TRY(hipGetLastError());
   return SSF_OK;
 }
 
@@ -1365,6 +1492,7 @@ struct BatchGroup {
 
 struct ssf_batch {
   int count = 0, dtype = 0, device = 0;
+  int vkind = ssf::V_CTAP;             // guide tables, or borrowed FP64 potential tables (V_TAB64)
   hipStream_t user = nullptr, cap = nullptr;
   hipEvent_t ev_start = nullptr, ev_fork = nullptr, ev_done = nullptr;
   std::vector<BatchGroup> groups;
@@ -1377,11 +1505,12 @@ struct ssf_batch {
 
 namespace {
 
-PassArgs batch_args(BatchGroup& G, int axis) {
+PassArgs batch_args(BatchGroup& G, int axis, int vkind) {
   PassArgs a = base_args(G.h, nullptr, nullptr, axis);
   a.inst = G.d_inst;
   a.ninst = (int)G.members.size();
-  a.vkind = ssf::V_CTAP;
+  a.vkind = vkind;
+  a.vtab = nullptr;
   a.nguides = ssf::MAX_GUIDES;
   return a;
 }
@@ -1389,27 +1518,27 @@ PassArgs batch_args(BatchGroup& G, int axis) {
 // k real-time Strang steps of every instance of the group (fused chain:
 // x forward with the half potential phase, k x (y, z, y) with the fused x
 // pass between steps, x inverse with the half phase).
-ssf_status batch_chunk(BatchGroup& G, int64_t k, double dt, const double2* kt) {
+ssf_status batch_chunk(BatchGroup& G, int vkind, int64_t k, double dt, const double2* kt) {
   ssf_handle* h = G.h;
-  PassArgs ax = batch_args(G, 0);
+  PassArgs ax = batch_args(G, 0, vkind);
   ax.pre = ssf::PRE_VPHASE;
   ax.cpre = 0.5 * dt;
   SSF_TRY(launch(h, ssf::CONTIG_FWD, 0, ax));
   for (int64_t s = 1; s <= k; ++s) {
-    PassArgs ay = batch_args(G, 1);
+    PassArgs ay = batch_args(G, 1, vkind);
     SSF_TRY(launch(h, ssf::STRIDED_FWD, 1, ay));
-    PassArgs az = batch_args(G, 2);
+    PassArgs az = batch_args(G, 2, vkind);
     az.mid = ssf::MID_KINETIC;
     az.kt[0] = kt;
     az.kt[1] = kt + h->n[0];
     az.kt[2] = kt + h->n[0] + h->n[1];
     SSF_TRY(launch(h, ssf::STRIDED_FUSED, 2, az));
     SSF_TRY(launch(h, ssf::STRIDED_INV, 1, ay));
-    PassArgs am = batch_args(G, 0);
+    PassArgs am = batch_args(G, 0, vkind);
     if (s < k) {
       am.mid = ssf::MID_VPHASE;
       am.cmid = dt;
-      am.small_phase = phase_tier(ssf::V_CTAP, G.vmax, dt);
+      am.small_phase = phase_tier(vkind, G.vmax, dt);
       SSF_TRY(launch(h, ssf::CONTIG_FUSED, 0, am));
     } else {
       am.post = ssf::POST_VPHASE;
@@ -1436,7 +1565,7 @@ ssf_status batch_join(ssf_batch* b) {
 
 ssf_status batch_chunks_all(ssf_batch* b, int64_t k, double dt, const std::vector<const double2*>& kts) {
   SSF_TRY(batch_fork(b));
-  for (size_t i = 0; i < b->groups.size(); ++i) SSF_TRY(batch_chunk(b->groups[i], k, dt, kts[i]));
+  for (size_t i = 0; i < b->groups.size(); ++i) SSF_TRY(batch_chunk(b->groups[i], b->vkind, k, dt, kts[i]));
   return batch_join(b);
 }
 
@@ -1473,14 +1602,23 @@ bool same_grid(const ssf_grid_desc& a, const ssf_grid_desc& c) {
 
 extern "C" {
 
-ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf_ctap_desc* guides,
-                            const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
-                            ssf_batch** out) {
-  if (!out || count < 1 || !grids || !guides || !x_lo || !x_hi) return fail(SSF_E_INVALID, "bad batch arguments");
+}  // extern "C"
+
+namespace {
+
+// Batch of instances with guide potentials (guides != nullptr) or borrowed
+// FP64 potential tables (vtabs != nullptr).
+ssf_status batch_create(int32_t count, const ssf_grid_desc* grids, const ssf_ctap_desc* guides,
+                        const double* const* vtabs, const double* x_lo, const double* x_hi, int32_t dtype,
+                        void* hip_stream, ssf_batch** out) {
+  if (!out || count < 1 || !grids || (!guides == !vtabs) || !x_lo || !x_hi)
+    return fail(SSF_E_INVALID, "bad batch arguments");
   *out = nullptr;
+  if (dtype != SSF_C64 && dtype != SSF_C128) return fail(SSF_E_INVALID, "dtype must be SSF_C64 or SSF_C128");
   ssf_batch* b = new ssf_batch();
   b->count = count;
   b->dtype = dtype;
+  b->vkind = vtabs ? ssf::V_TAB64 : ssf::V_CTAP;
   b->user = (hipStream_t)hip_stream;
   if (hipGetDevice(&b->device) != hipSuccess) { delete b; return fail(SSF_E_NODEVICE, "no HIP device"); }
   auto bail = [&](ssf_status st) { batch_free(b); return st; };
@@ -1509,11 +1647,22 @@ ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf
   }
   for (int i = 0; i < count; ++i) {
     BatchGroup& G = b->groups[gid[i]];
+    if (!(x_lo[i] <= x_hi[i])) return bail(fail(SSF_E_INVALID, "partition needs x_lo <= x_hi"));
+    ssf::InstDesc id;
+    std::memset(&id, 0, sizeof(id));
+    partition_indices(G.h, x_lo[i], x_hi[i], &id.ix_lo, &id.ix_hi);
+    if (vtabs) {
+      if (!vtabs[i] || ((uintptr_t)vtabs[i]) % sizeof(double) != 0)
+        return bail(fail(SSF_E_INVALID, "potential table null or misaligned"));
+      id.vtab = vtabs[i];
+      G.inst.push_back(id);
+      G.members.push_back(i);
+      continue;
+    }
     const ssf_ctap_desc* d = &guides[i];
     if (!d->xc || d->nguides < 1 || d->nguides > ssf::MAX_GUIDES) return bail(fail(SSF_E_INVALID, "bad guide description"));
     for (int q = 0; q < d->nguides; ++q)
       if (!(d->sigma[q] > 0.0) || !std::isfinite(d->v0[q])) return bail(fail(SSF_E_INVALID, "sigma must be > 0"));
-    if (!(x_lo[i] <= x_hi[i])) return bail(fail(SSF_E_INVALID, "partition needs x_lo <= x_hi"));
     std::vector<double> tab;
     const double vm = ctap_tables(G.h, d, tab);
     double* dev = nullptr;
@@ -1522,11 +1671,7 @@ ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf
     if (hipMemcpy(dev, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(SSF_E_DEVICE, "guide table upload"));
     G.vmax = std::max(G.vmax, vm);
-    ssf::InstDesc id;
-    id.in = nullptr;
-    id.out = nullptr;
     id.ctap = dev;
-    partition_indices(G.h, x_lo[i], x_hi[i], &id.ix_lo, &id.ix_hi);
     G.inst.push_back(id);
     G.members.push_back(i);
   }
@@ -1550,6 +1695,24 @@ ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf
   }
   *out = b;
   return SSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssf_status ssf_batch_create(int32_t count, const ssf_grid_desc* grids, const ssf_ctap_desc* guides,
+                            const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
+                            ssf_batch** out) {
+  if (!guides) return fail(SSF_E_INVALID, "bad batch arguments");
+  return batch_create(count, grids, guides, nullptr, x_lo, x_hi, dtype, hip_stream, out);
+}
+
+ssf_status ssf_batch_create_tables(int32_t count, const ssf_grid_desc* grids, const double* const* vtabs,
+                                   const double* x_lo, const double* x_hi, int32_t dtype, void* hip_stream,
+                                   ssf_batch** out) {
+  if (!vtabs) return fail(SSF_E_INVALID, "bad batch arguments");
+  return batch_create(count, grids, nullptr, vtabs, x_lo, x_hi, dtype, hip_stream, out);
 }
 
 ssf_status ssf_batch_set_stream(ssf_batch* b, void* hip_stream) {
@@ -1651,7 +1814,7 @@ ssf_status ssf_batch_run(ssf_batch* b, void* const* psi, int64_t nsteps, double 
   }
   if (obs_dev) {
     for (auto& G : b->groups) {
-      PassArgs a = batch_args(G, 0);
+      PassArgs a = batch_args(G, 0, b->vkind);
       a.partials = G.obs_part;
       const int rows = G.h->ks[0]->contig[G.h->dti].px;
       const dim3 gx = pass_grid(G.h, 0);

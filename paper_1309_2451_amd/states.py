@@ -59,3 +59,37 @@ def guide_transfer_state(torch, cfg, device, imag_steps=None, kz=None):
     phi = transverse_ground_state(torch, g.n[:2], g.lo[:2], g.hi[:2], gd.v0[0], gd.sigma[0], xc, steps, cfg["dt"],
                                   device)
     return packet(torch, g, phi, cfg["z0"], cfg["zwidth"], cfg["kz"] if kz is None else kz, device)
+
+
+def chip_guide_state(torch, cfg, device, steps=2000, wall=50.0):
+    """The atom-chip workload's initial state (Sec. V): the transverse ground
+    state of the left guide at z0, found by the library's imaginary-time step
+    on the transverse plane with the chip potential of that plane (walled off
+    by `wall` energy units beyond the midline between the left and the middle
+    wire, so the state settles in the left guide), times a Gaussian of width
+    zwidth along z at rest (the longitudinal trap sets it moving).
+    cfg: synth.config_chip(...) (grid, wires, fields, dt, z0, zwidth)."""
+    g = cfg["grid"]
+    nx, ny = g.n[0], g.n[1]
+    z0 = float(cfg["z0"])
+    dz = g.spacing(2)
+    s2 = Solver((nx, ny, 1), (g.lo[0], g.lo[1], z0), (g.hi[0], g.hi[1], z0 + dz), "c128", device=device)
+    try:
+        V = s2.chip_potential(cfg["paths"], cfg["currents"], cfg["b_bias"], cfg["b_ip"], cfg["length_unit"],
+                              cfg["mu_over_e0"], cfg["omega_z"], cfg["z_c"])
+        x = g.lo[0] + torch.arange(nx, dtype=torch.float64, device=device) * g.spacing(0)
+        y = g.lo[1] + torch.arange(ny, dtype=torch.float64, device=device) * g.spacing(1)
+        # wire positions in the plane z0 (linear along each polyline)
+        xw = [float(np.interp(z0, np.asarray(p)[:, 1], np.asarray(p)[:, 0])) for p in cfg["paths"]]
+        mid = 0.5 * (xw[0] + xw[1])
+        V = (V + wall * (x[None, None, :] >= mid).to(torch.float64)).contiguous()
+        s2.set_potential_table(V)
+        # start: a Gaussian under the left wire at the single-wire guide height
+        r0 = 2e-7 * float(cfg["currents"][0]) / float(cfg["b_bias"]) / float(cfg["length_unit"])
+        phi = torch.exp(-((x[None, :] - xw[0]) ** 2 + (y[:, None] - r0) ** 2) / (2 * 0.6 ** 2)).to(torch.complex128)
+        phi = phi.reshape(1, ny, nx).contiguous()
+        s2.step(phi, steps, cfg["dt"], imag=True)
+        torch.cuda.current_stream(device).synchronize()
+    finally:
+        s2.close()
+    return packet(torch, g, phi, z0, cfg["zwidth"], 0.0, device)

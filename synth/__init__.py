@@ -300,17 +300,23 @@ def chip_moment_for_period(units, b_bias=0.014, b_ip=0.03, current=0.1, period=0
     return omega ** 2 * b_ip / G ** 2
 
 
-def config_chip(i_mid=0.07, n=(256, 64, 1024), intuitive=False, i_outer=0.1):
+def config_chip(i_mid=0.07, n=(256, 64, 1024), intuitive=False, i_outer=0.1, height=8.0):
     """The three-wire 6Li atom chip of Secs. III and V: chip area 20 um x
-    1000 um (x, z), 4 um above the chip (y), wires 7 um apart approaching to
-    4.3 um, left wire straight 50 um longer, B_b = 0.014 T, B_ip = 0.03 T,
-    currents I_L = I_R = 0.1 A and I_M, longitudinal trap 2 pi x 5 Hz centred
-    at z = 500 um, dt = 1e-6 s for half a trap period (0.1 s, 10^5 steps).
-    Grid: x in [-10, 10) um, y from half a spacing above the chip surface
-    (so no grid point lies on a wire), z in [0, 1000) um."""
+    1000 um (x, z), wires 7 um apart approaching to 4.3 um, left wire
+    straight 50 um longer, B_b = 0.014 T, B_ip = 0.03 T, currents
+    I_L = I_R = 0.1 A and I_M, longitudinal trap 2 pi x 5 Hz centred at
+    z = 500 um, dt = 1e-6 s for half a trap period (0.1 s, 10^5 steps), on the
+    stated 256 x 64 x 1024 points.
+    Grid: x in [-10, 10) um, y from half a spacing above the chip surface (so
+    no grid point lies on a wire) up to `height` um, z in [0, 1000) um.  The
+    stated height is 4 um; with the moment scaled to the stated transverse
+    period (below) the potential above a guide rises only to ~5 energy units
+    at 4 um against a ground state at ~3.2, so in a 4 um periodic box the
+    state reaches the top and wraps onto the chip surface (V ~ 10^3 there),
+    which pumps energy into it; 8 um keeps the guides' states inside."""
     u = chip_units()
-    dy = 4.0 / n[1]
-    g = Grid(tuple(n), (-10.0, 0.5 * dy, 0.0), (10.0, 4.0 + 0.5 * dy, 1000.0))
+    dy = float(height) / n[1]
+    g = Grid(tuple(n), (-10.0, 0.5 * dy, 0.0), (10.0, float(height) + 0.5 * dy, 1000.0))
     paths = chip_wire_paths(intuitive=intuitive)
     omega_z = 2.0 * np.pi * 5.0 * u["t0"]
     dt = 1.0e-6 / u["t0"]
