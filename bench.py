@@ -455,12 +455,22 @@ def section_chip(torch, ssf, device, steps=2000, sweep_steps=1000, obs_every=100
     obs = b.obs_buffer()
     torch.cuda.synchronize()
     log("chip sweep: timed run, %d steps" % sweep_steps)
-    e0.record()
-    b.run(fields, sweep_steps, cfg["dt"], chunk=chunk, obs_buf=obs)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    rec = b.read_obs(obs)
+    # in segments of at most 10^4 steps (one observation of every instance at
+    # the end of each), each timed on torch's stream
+    seg = min(sweep_steps, 10000)
+    ms, done, p3_t, t_seg = 0.0, 0, [], []
+    while done < sweep_steps:
+        k = min(seg, sweep_steps - done)
+        e0.record()
+        b.run(fields, k, cfg["dt"], chunk=chunk, obs_buf=obs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done += k
+        rec = b.read_obs(obs)
+        p3_t.append([float(r["pop"][2]) for r in rec])
+        t_seg.append(done * 1e-6)
+        log("chip sweep: %d / %d steps" % (done, sweep_steps))
     b.close()
     n = len(cur)
     out["sweep"] = {
@@ -470,6 +480,7 @@ def section_chip(torch, ssf, device, steps=2000, sweep_steps=1000, obs_every=100
         "p3_counter_intuitive": [float(r["pop"][2]) for r in rec[:n]],
         "p3_intuitive": [float(r["pop"][2]) for r in rec[n:]],
         "mean_z": [float(r["mean"][2]) for r in rec],
+        "t_s": t_seg, "p3_vs_t": p3_t,
         "max_norm_drift": float(np.max(np.abs(np.array([r["norm"] for r in rec]) - 1.0))),
         "time_s": sweep_steps * 1e-6,
     }
