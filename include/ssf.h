@@ -176,15 +176,20 @@ ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
  * SSF_E_UNSUPPORTED while TVT is selected. */
 ssf_status ssf_set_splitting(ssf_handle* h, int32_t order);
 
-/* Tile autotuner.  The y and z passes come in NUM variants of tile shape
- * (0: 128 B of storage per row segment; 1: half-width tile, half the
- * workgroup and LDS, so twice as many workgroups fit a compute unit).  ssf_tune times
- * every variant of the y pass (forward) and of the z pass (forward-kinetic-
- * inverse) `reps` times on a field-sized workspace (allocated on first use),
- * keeps the fastest per axis, writes the choice to choice_out[3] (x is
- * always 0) and, if us_out != NULL, the average microseconds per launch to
- * us_out[axis * 2 + variant] (6 entries).  Synchronises the stream.
- * ssf_set_tiles / ssf_get_tiles set and read the choice (e.g. from a cache). */
+/* Tile autotuner.  The y and z passes come in SSF_TILE_VARIANTS variants of
+ * tile shape (0: 128 B of storage per row segment, the next tile prefetched
+ * into registers; 1: half-width tile, half the workgroup and LDS, so twice
+ * as many workgroups fit a compute unit; 2: the variant-0 tile with twice the
+ * values per thread and half the workgroup, no prefetch, complex64 values
+ * crossing LDS as FP32, so two workgroups share a compute unit).  ssf_tune
+ * times every variant of the y pass (forward) and of the z pass (forward-
+ * kinetic-inverse) `reps` times on a field-sized workspace (allocated on
+ * first use), keeps the fastest per axis, writes the choice to choice_out[3]
+ * (x is always 0) and, if us_out != NULL, the average microseconds per launch
+ * to us_out[axis * SSF_TILE_VARIANTS + variant] (3 x SSF_TILE_VARIANTS
+ * entries).  Synchronises the stream.  ssf_set_tiles / ssf_get_tiles set and
+ * read the choice (e.g. from a cache). */
+#define SSF_TILE_VARIANTS 3
 ssf_status ssf_tune(ssf_handle* h, int32_t reps, int32_t* choice_out, double* us_out);
 ssf_status ssf_set_tiles(ssf_handle* h, const int32_t* choice);
 ssf_status ssf_get_tiles(ssf_handle* h, int32_t* choice);

@@ -213,10 +213,11 @@ class Solver:
         """Time every y/z tile variant on this grid and keep the fastest.
         Returns (choice[3], {(axis, variant): microseconds})."""
         self._sync_stream()
+        nv = _ssf.SSF_TILE_VARIANTS
         ch = np.zeros(3, dtype=np.int32)
-        us = np.zeros(6, dtype=np.float64)
+        us = np.zeros(3 * nv, dtype=np.float64)
         _ssf.call("ssf_tune", self.h, int(reps), ctypes.c_void_p(ch.ctypes.data), ctypes.c_void_p(us.ctypes.data))
-        return ch.tolist(), {(a, v): float(us[a * 2 + v]) for a in (1, 2) for v in (0, 1)}
+        return ch.tolist(), {(a, v): float(us[a * nv + v]) for a in (1, 2) for v in range(nv)}
 
     def set_tiles(self, choice):
         ch = np.ascontiguousarray(choice, dtype=np.int32)

@@ -29,6 +29,7 @@ SSF_REAL = 0
 SSF_IMAG = 1
 SSF_SPLIT_VTV = 0
 SSF_SPLIT_TVT = 1
+SSF_TILE_VARIANTS = 3
 
 EXPORTS = (
     "ssf_supported_length", "ssf_create", "ssf_destroy", "ssf_set_stream",

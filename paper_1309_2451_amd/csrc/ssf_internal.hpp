@@ -81,8 +81,10 @@ struct PassShape {
 };
 
 // Strided tile variants (chosen per axis by the autotuner): 0 = px columns of
-// 128 B of storage; 1 = half as many columns (half the workgroup and LDS).
-constexpr int NUM_STRIDED_VARIANTS = 2;
+// 128 B of storage; 1 = half as many columns (half the workgroup and LDS);
+// 2 = the variant-0 tile with twice the values per thread, no register
+// prefetch, FP32 LDS exchanges for complex64 (two workgroups per CU).
+constexpr int NUM_STRIDED_VARIANTS = 3;
 
 struct KernelSet {
   int N;

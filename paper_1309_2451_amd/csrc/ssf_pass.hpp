@@ -87,6 +87,9 @@ template <class PL, bool REV> struct Order {
 #ifndef SSF_TILE_INTERLEAVE
 #define SSF_TILE_INTERLEAVE 1  // y/z workgroups take every gridDim-th tile (0: a contiguous range)
 #endif
+#ifndef SSF_X32
+#define SSF_X32 1              // FP32 double-buffered LDS exchanges in fused strided passes (complex64)
+#endif
 
 // Tile shapes.  LDS holds P pencils of N FP64 complex values.
 constexpr int LDS_CAP_ELEMS = 8192;       // 128 KiB of double2
@@ -117,7 +120,14 @@ template <int N> struct Shape {
   // the workgroup and half the LDS, so twice as many workgroups share a CU
   static constexpr bool v1(int dt) { return sx0(dt) > 1; }
   static constexpr int sx(int dt, int var = 0) { return (var == 1 && v1(dt)) ? sx0(dt) / 2 : sx0(dt); }
-  static constexpr int sm(int dt, int /*var*/ = 0) { return sm0(dt); }
+  // variant 2: the variant-0 tile with twice the values per thread (at most
+  // 16), half the workgroup, no register prefetch and (complex64) an FP32
+  // LDS buffer of half the bytes, so two workgroups share a CU and one's
+  // arithmetic overlaps the other's memory traffic instead of a prefetch
+  static constexpr int sm(int dt, int var = 0) {
+    return (var == 2 && Plan<N>::E * sm0(dt) * 2 <= 16 && N % (Plan<N>::E * sm0(dt) * 2) == 0) ? 2 * sm0(dt)
+                                                                                                : sm0(dt);
+  }
   static constexpr int ldrow() { return N; }
   static constexpr int cr() {              // contiguous rows per workgroup
     int rows = 256 * E / N;
@@ -531,12 +541,25 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2*
 }
 
 // Write the outputs of stage s-1 to LDS and read the inputs of stage s.
-template <class G, class ORD, int s>
-__device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds) {
+//
+// X32 (complex64 storage, fused strided passes): the values cross LDS
+// rounded to FP32 -- half the LDS bytes -- in two buffers that alternate
+// from one exchange to the next (xp counts the exchanges), so the barrier
+// after the reads is not needed: the next exchange writes the other buffer,
+// and the one after it comes after a barrier that every thread reaches only
+// once its reads of this buffer are done.  The FP64 exchange uses one buffer
+// and a barrier after the reads.
+//
+// XB: 0 = FP64, one buffer; 1 = FP32, two alternating buffers; 2 = FP32, one
+// buffer (a barrier after the reads, as FP64).
+template <class G, class ORD, int s, int XB>
+__device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds, int& xp) {
   constexpr int N = G::NN;
   constexpr int r1 = ORD::r(s - 1), p1 = ORD::p(s - 1);
   constexpr int r2 = ORD::r(s);
   constexpr int E = G::E;
+  constexpr bool X32 = XB != 0;
+  float2* l32 = (float2*)lds + (XB == 1 && (xp & 1) ? G::P * N : 0);
 #pragma unroll
   for (int u = 0; u < E / r1; ++u) {
     int b, i;
@@ -544,7 +567,11 @@ __device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds) {
     const int k = i % p1;
     const int j = (i - k) * r1 + k;
 #pragma unroll
-    for (int q = 0; q < r1; ++q) lds[G::lidx(b, j + q * p1)] = v[u * r1 + q];
+    for (int q = 0; q < r1; ++q) {
+      const double2 w = v[u * r1 + q];
+      if constexpr (X32) l32[G::lidx(b, j + q * p1)] = make_float2((float)w.x, (float)w.y);
+      else lds[G::lidx(b, j + q * p1)] = w;
+    }
   }
   lds_sync<G::WAVELOCAL>();
 #pragma unroll
@@ -552,33 +579,41 @@ __device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds) {
     int b, i;
     G::template map<r2>(u, b, i);
 #pragma unroll
-    for (int m = 0; m < r2; ++m) v[u * r2 + m] = lds[G::lidx(b, i + m * (N / r2))];
+    for (int m = 0; m < r2; ++m) {
+      if constexpr (X32) {
+        const float2 w = l32[G::lidx(b, i + m * (N / r2))];
+        v[u * r2 + m] = make_double2((double)w.x, (double)w.y);
+      } else {
+        v[u * r2 + m] = lds[G::lidx(b, i + m * (N / r2))];
+      }
+    }
   }
-  lds_sync<G::WAVELOCAL>();
+  if constexpr (XB == 1) ++xp;
+  else lds_sync<G::WAVELOCAL>();
 }
 
 // All stages of one transform direction; v holds the inputs of stage 0 on
 // entry and the outputs of the last stage on exit.
-template <class G, bool INV, bool REV>
-__device__ __forceinline__ void transform(double2 (&v)[G::E], double2* lds, const double2* __restrict__ tw) {
+template <class G, bool INV, bool REV, int XB = 0>
+__device__ __forceinline__ void transform(double2 (&v)[G::E], double2* lds, const double2* __restrict__ tw, int& xp) {
   using ORD = Order<Plan<G::NN>, REV>;
   constexpr int NS = Plan<G::NN>::S;
   static_assert(NS <= 5, "at most 5 stages");
   compute_stage<G, INV, ORD, 0>(v, tw);
   if constexpr (NS > 1) {
-    exchange<G, ORD, 1>(v, lds);
+    exchange<G, ORD, 1, XB>(v, lds, xp);
     compute_stage<G, INV, ORD, 1>(v, tw);
   }
   if constexpr (NS > 2) {
-    exchange<G, ORD, 2>(v, lds);
+    exchange<G, ORD, 2, XB>(v, lds, xp);
     compute_stage<G, INV, ORD, 2>(v, tw);
   }
   if constexpr (NS > 3) {
-    exchange<G, ORD, 3>(v, lds);
+    exchange<G, ORD, 3, XB>(v, lds, xp);
     compute_stage<G, INV, ORD, 3>(v, tw);
   }
   if constexpr (NS > 4) {
-    exchange<G, ORD, 4>(v, lds);
+    exchange<G, ORD, 4, XB>(v, lds, xp);
     compute_stage<G, INV, ORD, 4>(v, tw);
   }
 }
@@ -720,9 +755,16 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 
 // VT (with LEAN, fused x pass): the potential comes from an FP64 table in
 // global memory; each tile's values at the mid-op positions are prefetched
 // with the tile, so the table read overlaps the arithmetic like the field's.
+//
+// SV (strided passes): tile variant; variant 2 loads each tile when it gets
+// to it (no register prefetch) and, with complex64 storage, exchanges
+// through one FP32 buffer (XB = 2).
+//
+// Variant 2 kernels are built for four waves per SIMD (at most 128 VGPRs),
+// so that two of their half-size workgroups fit a CU.
 template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH,
-          bool VT = false>
-__global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM))
+          bool VT = false, int SV = 0>
+__global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM), SV == 2 ? 4 : 1)
 pass_kernel(PassArgs a) {
   using G = PassGeom<S, N, PX, PO, CONTIG, EM>;
   using PL = Plan<N>;
@@ -734,13 +776,24 @@ pass_kernel(PassArgs a) {
   constexpr int UM = E / rm;
   constexpr bool LOWP = sizeof(S) == 8;                            // complex64 storage: shorter phase series
 
-  __shared__ double2 lds[G::LDS];
+  // LDS exchanges of complex64 strided passes: variant 2 through one FP32
+  // buffer (half the bytes); fused passes otherwise through two alternating
+  // FP32 buffers (the bytes of one FP64 buffer); everything else FP64
+  constexpr bool C64S = !CONTIG && sizeof(S) == 8 && PL::S > 1;
+  constexpr int XB = (C64S && SV == 2) ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0);
+  constexpr bool PF = SV != 2;                                     // register prefetch of the next tile
+  int xpar = 0;
+  __shared__ double2 lds[XB == 2 ? (G::LDS + 1) / 2 : G::LDS];
   // Power-of-two plans read twiddle powers W^t only for t < N/2 (the
   // products of lower powers are formed in registers), so half the table.
   constexpr int TWN = (!SSF_TW_FULL && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N;
   __shared__ double2 s_tw[TWN];
   __shared__ double2 s_kz[KZ ? N : 1];
-  __shared__ double s_A[CONTIG ? MAX_GUIDES * N : 1];
+  // Lean fused x pass whose waves own one row each (64 E = N): the guide
+  // factors B_g(y) of the wave's row are read with scalar loads, so the B
+  // table takes no LDS (at N = 512 that lets a third workgroup onto a CU).
+  constexpr bool BSC = CONTIG && LEAN && !VT && G::WAVELOCAL && G::PPW == 1;
+  __shared__ double s_A[(CONTIG && !VT) ? MAX_GUIDES * N : 1];
   __shared__ double red[((WG + 63) / 64) * NRED_OBS];
   extern __shared__ double s_dyn[];                                // x passes: B_g(y), MAX_GUIDES * ny
 
@@ -816,8 +869,8 @@ pass_kernel(PassArgs a) {
   };
   // the adjoint and global potential tables read global memory inside the
   // tile, so those passes load each tile when they reach it
-  const bool prefetch = LEAN || !(CONTIG && ((a.pre & PRE_ADJ) || (a.post & POST_ADJ) ||
-                                             (!ctap && a.vkind != V_NONE)));
+  const bool prefetch = PF && (LEAN || !(CONTIG && ((a.pre & PRE_ADJ) || (a.post & POST_ADJ) ||
+                                                   (!ctap && a.vkind != V_NONE))));
 
   int plane = -1, binst = -1;
   if (prefetch) load_tile(tbeg);
@@ -839,7 +892,7 @@ pass_kernel(PassArgs a) {
         const double* A = BATCH ? idesc[k].ctap : a.ctapA;
         for (int j = threadIdx.x; j < MAX_GUIDES * N; j += WG)
           s_A[j] = ldg(A + (j / N) * pl + (long long)t1 * a.nx + (j % N));
-        if (k != binst) {
+        if (!BSC && k != binst) {
           const double* B = BATCH ? idesc[k].ctap + 2 * gplane : a.ctapB;
           for (int j = threadIdx.x; j < MAX_GUIDES * a.ny; j += WG) s_dyn[j] = ldg(B + j);
         }
@@ -884,7 +937,7 @@ pass_kernel(PassArgs a) {
       }
     }
 
-    transform<G, INV1, false>(v, lds, s_tw);
+    transform<G, INV1, false, XB>(v, lds, s_tw, xpar);
 
     if constexpr (FUSED) {
       // outputs of the last stage sit at n = i + q N / rm
@@ -899,10 +952,25 @@ pass_kernel(PassArgs a) {
             for (int e = 0; e < E; ++e) V[e] = vcur[e];
           } else if constexpr (LEAN) {
             // guide potential from LDS (the host selects LEAN only for it or for V = 0)
+            const double SSF_CONST* Bs =
+                (const double SSF_CONST*)(BATCH ? idesc[k].ctap + 2 * gplane : a.ctapB);
 #pragma unroll
             for (int u = 0; u < UM; ++u) {
-              const int y = p.c0[u];
-              const double b0 = s_dyn[y], b1 = s_dyn[a.ny + y], b2 = s_dyn[2 * a.ny + y];
+              double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+              if constexpr (BSC) {
+                // one row per wave: y is uniform, the loads are scalar
+                const int y = __builtin_amdgcn_readfirstlane(p.c0[u]);
+                if (ctap) {
+                  b0 = Bs[y];
+                  b1 = Bs[a.ny + y];
+                  b2 = Bs[2 * a.ny + y];
+                }
+              } else {
+                const int y = p.c0[u];
+                b0 = s_dyn[y];
+                b1 = s_dyn[a.ny + y];
+                b2 = s_dyn[2 * a.ny + y];
+              }
 #pragma unroll
               for (int m = 0; m < rm; ++m) {
                 const int x = p.i[u] + m * (N / rm);
@@ -954,7 +1022,7 @@ pass_kernel(PassArgs a) {
           }
         }
       }
-      transform<G, !INV1, true>(v, lds, s_tw);
+      transform<G, !INV1, true, XB>(v, lds, s_tw, xpar);
     }
 
     // ---- post ops + store (outputs of the last stage at n = i + q N / rl) ----
@@ -1099,16 +1167,18 @@ hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t s
   switch (kind) {
     case STRIDED_FWD:
       if (a.post == 0)
-        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true, B>, WGS, 0, a, tiles, st,
-                                 occ[0]);
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true, B, false, VAR>, WGS, 0, a,
+                                 tiles, st, occ[0]);
       if constexpr (B) return hipErrorInvalidValue;
       else
-        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false, false>, WGS, 0, a, tiles,
-                                 st, occ[1]);
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false, false, false, VAR>, WGS, 0,
+                                 a, tiles, st, occ[1]);
     case STRIDED_INV:
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true, B>, WGS, 0, a, tiles, st, occ[2]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true, B, false, VAR>, WGS, 0, a, tiles,
+                               st, occ[2]);
     case STRIDED_FUSED:
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true, B>, WGS, 0, a, tiles, st, occ[3]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true, B, false, VAR>, WGS, 0, a, tiles,
+                               st, occ[3]);
     default:
       return hipErrorInvalidValue;
   }
@@ -1126,6 +1196,9 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
   constexpr int WGC = PassGeom<S, N, CR, 1, true, 1>::WG;
   const size_t dync = sizeof(double) * MAX_GUIDES * (size_t)a.ny;
   static OccCache occ[5];
+  using GX = PassGeom<S, N, CR, 1, true, 1>;
+  // the lean kernels that keep no B_g(y) table in LDS (scalar loads, or a potential table)
+  const size_t dyn_bsc = (GX::WAVELOCAL && GX::PPW == 1) ? 0 : dync;
   const bool lean_x = a.pre == 0 && a.post == 0 && !a.imag && (a.vkind == V_CTAP || a.vkind == V_NONE);
   const bool lean_t = a.pre == 0 && a.post == 0 && !a.imag && a.vkind == V_TAB64 && a.mid == MID_VPHASE;
   switch (kind) {
@@ -1137,18 +1210,19 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
                                occ[1]);
     case CONTIG_FUSED:
       if (lean_x)
-        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B>, WGC, dync, a, tiles, st,
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B>, WGC, dyn_bsc, a, tiles, st,
                                  occ[2]);
       if (lean_t)
-        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B, true>, WGC, dync, a, tiles,
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B, true>, WGC, 0, a, tiles,
                                  st, occ[4]);
       if constexpr (B) return hipErrorInvalidValue;
       else
         return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false, false>, WGC, dync, a, tiles, st,
                                  occ[3]);
     default:
-      return variant == 1 ? launch_strided<S, N, DT, 1, B>(kind, a, tiles, st)
-                          : launch_strided<S, N, DT, 0, B>(kind, a, tiles, st);
+      return variant == 2   ? launch_strided<S, N, DT, 2, B>(kind, a, tiles, st)
+             : variant == 1 ? launch_strided<S, N, DT, 1, B>(kind, a, tiles, st)
+                            : launch_strided<S, N, DT, 0, B>(kind, a, tiles, st);
   }
 }
 
@@ -1174,7 +1248,8 @@ constexpr KernelSet make_kernel_set() {
       N,
       {PassShape{Shape<N>::cr(), 1, PassGeom<float2, N, Shape<N>::cr(), 1, true, 1>::WG},
        PassShape{Shape<N>::cr(), 1, PassGeom<double2, N, Shape<N>::cr(), 1, true, 1>::WG}},
-      {{strided_shape<N, 0, 0>(), strided_shape<N, 0, 1>()}, {strided_shape<N, 1, 0>(), strided_shape<N, 1, 1>()}},
+      {{strided_shape<N, 0, 0>(), strided_shape<N, 0, 1>(), strided_shape<N, 0, 2>()},
+       {strided_shape<N, 1, 0>(), strided_shape<N, 1, 1>(), strided_shape<N, 1, 2>()}},
       &launch_any<N>};
 }
 

@@ -25,6 +25,8 @@
 using ssf::PassArgs;
 using ssf::KernelSet;
 
+static_assert(ssf::NUM_STRIDED_VARIANTS == SSF_TILE_VARIANTS, "tile variant count of the C ABI");
+
 namespace {
 
 thread_local std::string g_last_error;

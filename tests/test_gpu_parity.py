@@ -361,7 +361,7 @@ def test_tile_variants_and_tuner(dtype, shape):
     s = ssf.Solver(g.n, g.lo, g.hi, dtype)
     s.set_potential_table(torch.from_numpy(V).to(DEV))
     ref_step, _ = oracle.step(psi0, V, g.lo, g.hi, 0.01, 20)
-    for choice in ([0, 1, 1], [0, 0, 1], [0, 1, 0]):
+    for choice in ([0, 1, 1], [0, 0, 1], [0, 1, 0], [0, 2, 2], [0, 2, 0], [0, 0, 2]):
         s.set_tiles(choice)
         assert s.get_tiles() == choice
         for axis in (1, 2):
@@ -372,7 +372,7 @@ def test_tile_variants_and_tuner(dtype, shape):
         s.step(t, 20, 0.01)
         assert rel(host(t), ref_step) < tol_step, choice
     choice, us = s.tune(reps=2)
-    assert choice[0] == 0 and choice[1] in (0, 1) and choice[2] in (0, 1)
+    assert choice[0] == 0 and choice[1] in (0, 1, 2) and choice[2] in (0, 1, 2)
     assert all(v > 0 for v in us.values())
     t = to_dev(psi0, s)
     s.step(t, 20, 0.01)
