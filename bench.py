@@ -97,7 +97,7 @@ def c2_initial_state(torch, ssf, cfg, device):
 # one timed run of a single field
 # ---------------------------------------------------------------------------
 def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tune=True, timing=True,
-              splitting="vtv", tiles=None, window=0):
+              splitting="vtv", tiles=None, window=0, arith="f64"):
     """One storage type on the workload: tile choice (autotuner unless `tiles`
     is given), then `window` steps with per-pass HIP events on a scratch copy
     (the steady-state pass times of the roofline entry), `warmup` untimed
@@ -105,6 +105,8 @@ def timed_run(torch, ssf, cfg, psi0, dtype, steps, warmup, obs_every, device, tu
     g, gd = cfg["grid"], cfg["guides"]
     s = ssf.Solver(g.n, g.lo, g.hi, dtype, device=device)
     s.set_splitting(splitting)
+    if arith != "f64":
+        s.set_arithmetic(arith)
     s.set_guides(gd.v0, gd.sigma, gd.xc)
     s.set_partition(gd.x_lo, gd.x_hi)
     tune_info = None
@@ -806,7 +808,17 @@ def main():
             "c64_speedup_vs_c128": q128["ms"] / q64["ms"],
             "targets": {"rel_l2": 1e-4, "abs_norm_drift": 1e-5},
             "met": bool(l2 <= 1e-4 and abs(d64) <= 1e-5)}
-        del runs, q64, q128
+        # the same steps with complex64 bulk arithmetic in FP32 (FP64 phases and sums)
+        log("accuracy: %d steps in complex64 with FP32 arithmetic" % n_acc)
+        q32 = timed_run(torch, ssf, cfg, psi0, "c64", n_acc, 0, a.obs_every, device, timing=False, arith="f32")
+        l2f = rel_l2(torch, q32["psi"], q128["psi"])
+        d32 = float(q32["rec"][-1]["norm"] - 1.0)
+        p32 = float(q32["rec"][-1]["pop"][2])
+        out["accuracy_1e4"]["fp32_arithmetic"] = {
+            "rel_l2_vs_c128": l2f, "norm_drift": d32, "p3": p32, "p3_abs_err": abs(p32 - p128),
+            "ms_per_step": q32["ms"] / n_acc, "speedup_vs_fp64_arithmetic": q64["ms"] / q32["ms"],
+            "tiles": q32["tune"]["choice"], "met": bool(l2f <= 1e-4 and abs(d32) <= 1e-5)}
+        del runs, q64, q128, q32
         torch.cuda.empty_cache()
     # the library's plain copy of one complex64 field: the bandwidth a pass
     # that only streams the field in and out reaches on this device (timed on

@@ -175,6 +175,20 @@ ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps);
  * time, ssf_step_ckpt, ssf_step_seq and the adjoint use VTV only and return
  * SSF_E_UNSUPPORTED while TVT is selected. */
 ssf_status ssf_set_splitting(ssf_handle* h, int32_t order);
+/* Arithmetic of a complex64 handle's passes.  SSF_ARITH_F64 (default): every
+ * butterfly, twiddle and factor multiplication in FP64 registers, values
+ * rounded to complex64 once per pass.  SSF_ARITH_F32: complex64 bulk
+ * arithmetic -- butterflies, twiddle products and LDS exchanges in FP32, every
+ * twiddle power an exactly rounded FP32 value of an FP64 table -- while the
+ * phase arguments (V dt, k^2 dt) are formed and reduced modulo 2 pi in FP64,
+ * each phase or kinetic factor is computed in FP64 and rounded once, and all
+ * reductions accumulate in FP64.  Faster in registers, less accurate (the
+ * per-step rounding of FP32 transforms accumulates; see the design notes for
+ * measured errors).  Single handles only (batches use FP64).  Errors: INVALID
+ * (unknown mode, FP32 on a complex128 handle). */
+#define SSF_ARITH_F64 0
+#define SSF_ARITH_F32 1
+ssf_status ssf_set_arithmetic(ssf_handle* h, int32_t arith);
 
 /* Tile autotuner.  The y and z passes come in SSF_TILE_VARIANTS variants of
  * tile shape (0: 128 B of storage per row segment, the next tile prefetched

@@ -209,6 +209,11 @@ class Solver:
         """"vtv" (default: V/2-T-V/2) or "tvt" (T/2-V-T/2) for real-time steps."""
         _ssf.call("ssf_set_splitting", self.h, {"vtv": _ssf.SSF_SPLIT_VTV, "tvt": _ssf.SSF_SPLIT_TVT}[order])
 
+    def set_arithmetic(self, mode: str):
+        """"f64" (default) or "f32" (complex64 handles: FP32 bulk arithmetic,
+        FP64 phase arguments, factors and sums)."""
+        _ssf.call("ssf_set_arithmetic", self.h, {"f64": _ssf.SSF_ARITH_F64, "f32": _ssf.SSF_ARITH_F32}[mode])
+
     def tune(self, reps=5):
         """Time every y/z tile variant on this grid and keep the fastest.
         Returns (choice[3], {(axis, variant): microseconds})."""

@@ -30,6 +30,8 @@ SSF_IMAG = 1
 SSF_SPLIT_VTV = 0
 SSF_SPLIT_TVT = 1
 SSF_TILE_VARIANTS = 3
+SSF_ARITH_F64 = 0
+SSF_ARITH_F32 = 1
 
 EXPORTS = (
     "ssf_supported_length", "ssf_create", "ssf_destroy", "ssf_set_stream",
@@ -40,7 +42,7 @@ EXPORTS = (
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
     "ssf_batch_info", "ssf_batch_set_stream", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_bspline_eval", "ssf_status_string", "ssf_last_error",
     "ssf_step_noalloc", "ssf_noalloc_scratch_bytes", "ssf_noalloc_scratch_need",
-    "ssf_chip_potential", "ssf_batch_create_tables",
+    "ssf_chip_potential", "ssf_batch_create_tables", "ssf_set_arithmetic",
 )
 
 
@@ -109,6 +111,7 @@ def load():
         "ssf_set_partition_z": ([hp, dp, dp], i32),
         "ssf_set_fusion": ([hp, i32], i32),
         "ssf_set_splitting": ([hp, i32], i32),
+        "ssf_set_arithmetic": ([hp, i32], i32),
         "ssf_set_timing": ([hp, i32], i32),
         "ssf_tune": ([hp, i32, vp, vp], i32),
         "ssf_set_tiles": ([hp, vp], i32),

@@ -141,30 +141,49 @@ template <int N> struct Shape {
 };
 
 // ---------------------------------------------------------------------------
-// Complex helpers (FP64).
+// Complex helpers, for the register type C of a pass: double2 (FP64
+// arithmetic, the default for both storage types) or float2 (FP32
+// arithmetic, a selectable mode for complex64 storage).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <class C> struct Cx;
+template <> struct Cx<double2> {
+  using R = double;
+  __device__ static __forceinline__ double2 mk(double x, double y) { return make_double2(x, y); }
+};
+template <> struct Cx<float2> {
+  using R = float;
+  __device__ static __forceinline__ float2 mk(float x, float y) { return make_float2(x, y); }
+};
+// a complex value formed in FP64 (a phase factor, a table entry) in register type C
+template <class C> __device__ __forceinline__ C to_c(double2 d) {
+  return Cx<C>::mk((typename Cx<C>::R)d.x, (typename Cx<C>::R)d.y);
 }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+template <class C> __device__ __forceinline__ double2 to_d(C v) { return make_double2((double)v.x, (double)v.y); }
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { return Cx<C>::mk(a.x + b.x, a.y + b.y); }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { return Cx<C>::mk(a.x - b.x, a.y - b.y); }
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+  return Cx<C>::mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <class C> __device__ __forceinline__ C cscale(C a, double s) {
+  const typename Cx<C>::R t = (typename Cx<C>::R)s;
+  return Cx<C>::mk(a.x * t, a.y * t);
+}
+template <class C> __device__ __forceinline__ C conj2(C a) { return Cx<C>::mk(a.x, -a.y); }
 // multiply by -i (forward) or +i (inverse)
-template <bool INV> __device__ __forceinline__ double2 mul_mi(double2 a) {
-  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <bool INV, class C> __device__ __forceinline__ C mul_mi(C a) {
+  return INV ? Cx<C>::mk(-a.y, a.x) : Cx<C>::mk(a.y, -a.x);
 }
 // multiply by exp(-/+ i pi/4) * sqrt2 ... as rotation by w8 = exp(-/+ 2 pi i / 8)
 constexpr double SQRT1_2 = 0.70710678118654752440084436210485;
-template <bool INV> __device__ __forceinline__ double2 mul_w8_1(double2 a) {
+template <bool INV, class C> __device__ __forceinline__ C mul_w8_1(C a) {
   // fwd: (1 - i)/sqrt2, inv: (1 + i)/sqrt2
-  return INV ? make_double2((a.x - a.y) * SQRT1_2, (a.x + a.y) * SQRT1_2)
-             : make_double2((a.x + a.y) * SQRT1_2, (a.y - a.x) * SQRT1_2);
+  const typename Cx<C>::R h = (typename Cx<C>::R)SQRT1_2;
+  return INV ? Cx<C>::mk((a.x - a.y) * h, (a.x + a.y) * h) : Cx<C>::mk((a.x + a.y) * h, (a.y - a.x) * h);
 }
-template <bool INV> __device__ __forceinline__ double2 mul_w8_3(double2 a) {
+template <bool INV, class C> __device__ __forceinline__ C mul_w8_3(C a) {
   // fwd: (-1 - i)/sqrt2, inv: (-1 + i)/sqrt2
-  return INV ? make_double2((-a.x - a.y) * SQRT1_2, (a.x - a.y) * SQRT1_2)
-             : make_double2((a.y - a.x) * SQRT1_2, (-a.x - a.y) * SQRT1_2);
+  const typename Cx<C>::R h = (typename Cx<C>::R)SQRT1_2;
+  return INV ? Cx<C>::mk((-a.x - a.y) * h, (a.x - a.y) * h) : Cx<C>::mk((a.y - a.x) * h, (-a.x - a.y) * h);
 }
 
 // Storage conversions.  Field and table pointers may come from a batch
@@ -194,9 +213,14 @@ __device__ __forceinline__ void st2(double2* p, double2 v) {
   const d2v_t t = {v.x, v.y};
   *(SSF_GLOBAL d2v_t*)p = t;
 }
-// Value as it is after rounding to storage (for reductions that must see the stored field).
+__device__ __forceinline__ void st2(float2* p, float2 v) {
+  const f2v_t t = {v.x, v.y};
+  *(SSF_GLOBAL f2v_t*)p = t;
+}
+// Value as it is after rounding to storage (for reductions that must see the stored field), in FP64.
 __device__ __forceinline__ double2 rounded(double2 v, const float2*) { return make_double2((double)(float)v.x, (double)(float)v.y); }
 __device__ __forceinline__ double2 rounded(double2 v, const double2*) { return v; }
+__device__ __forceinline__ double2 rounded(float2 v, const float2*) { return make_double2((double)v.x, (double)v.y); }
 
 // ---------------------------------------------------------------------------
 // Small DFTs: y_q = sum_m x_m exp(sign 2 pi i m q / r), in place, sign = -1
@@ -204,20 +228,22 @@ __device__ __forceinline__ double2 rounded(double2 v, const double2*) { return v
 // ---------------------------------------------------------------------------
 template <int R, bool INV> struct Bfly;
 
-template <bool INV> struct Bfly<1, INV> { __device__ static void run(double2*) {} };
+template <bool INV> struct Bfly<1, INV> {
+  template <class C> __device__ static void run(C*) {}
+};
 
 template <bool INV> struct Bfly<2, INV> {
-  __device__ static void run(double2* x) {
-    double2 a = x[0], b = x[1];
+  template <class C> __device__ static void run(C* x) {
+    C a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
   }
 };
 
 template <bool INV> struct Bfly<4, INV> {
-  __device__ static void run(double2* x) {
-    double2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
-    double2 t2 = cadd(x[1], x[3]), t3 = mul_mi<INV>(csub(x[1], x[3]));
+  template <class C> __device__ static void run(C* x) {
+    C t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+    C t2 = cadd(x[1], x[3]), t3 = mul_mi<INV>(csub(x[1], x[3]));
     x[0] = cadd(t0, t2);
     x[2] = csub(t0, t2);
     x[1] = cadd(t1, t3);
@@ -226,9 +252,9 @@ template <bool INV> struct Bfly<4, INV> {
 };
 
 template <bool INV> struct Bfly<8, INV> {
-  __device__ static void run(double2* x) {
-    double2 e[4] = {x[0], x[2], x[4], x[6]};
-    double2 o[4] = {x[1], x[3], x[5], x[7]};
+  template <class C> __device__ static void run(C* x) {
+    C e[4] = {x[0], x[2], x[4], x[6]};
+    C o[4] = {x[1], x[3], x[5], x[7]};
     Bfly<4, INV>::run(e);
     Bfly<4, INV>::run(o);
     o[1] = mul_w8_1<INV>(o[1]);
@@ -249,15 +275,15 @@ __device__ constexpr double S16[8] = {0.0, 0.38268343236508977173, 0.70710678118
                                       1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
 
 template <bool INV> struct Bfly<16, INV> {
-  __device__ static void run(double2* x) {
-    double2 e[8], o[8];
+  template <class C> __device__ static void run(C* x) {
+    C e[8], o[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) { e[q] = x[2 * q]; o[q] = x[2 * q + 1]; }
     Bfly<8, INV>::run(e);
     Bfly<8, INV>::run(o);
 #pragma unroll
     for (int q = 1; q < 8; ++q) {
-      double2 w = make_double2(C16[q], INV ? S16[q] : -S16[q]);
+      const C w = to_c<C>(make_double2(C16[q], INV ? S16[q] : -S16[q]));
       o[q] = cmul(o[q], w);
     }
 #pragma unroll
@@ -270,12 +296,13 @@ template <bool INV> struct Bfly<16, INV> {
 
 constexpr double SIN_2PI_3 = 0.86602540378443864676372317075294;  // sqrt(3)/2
 template <bool INV> struct Bfly<3, INV> {
-  __device__ static void run(double2* x) {
-    double2 t = cadd(x[1], x[2]);
-    double2 s = csub(x[1], x[2]);
-    double2 a = make_double2(x[0].x - 0.5 * t.x, x[0].y - 0.5 * t.y);
+  template <class C> __device__ static void run(C* x) {
+    using R = typename Cx<C>::R;
+    C t = cadd(x[1], x[2]);
+    C s = csub(x[1], x[2]);
+    C a = Cx<C>::mk(x[0].x - (R)0.5 * t.x, x[0].y - (R)0.5 * t.y);
     // fwd: y1 = a - i (sqrt3/2) s, y2 = a + i (sqrt3/2) s
-    double2 b = mul_mi<INV>(cscale(s, SIN_2PI_3));
+    C b = mul_mi<INV>(cscale(s, SIN_2PI_3));
     x[0] = cadd(x[0], t);
     x[1] = cadd(a, b);
     x[2] = csub(a, b);
@@ -287,16 +314,18 @@ constexpr double C2_5 = -0.80901699437494742410229341718282;  // cos(4 pi / 5)
 constexpr double S1_5 = 0.95105651629515357211643933337938;   // sin(2 pi / 5)
 constexpr double S2_5 = 0.58778525229247312916870595463907;   // sin(4 pi / 5)
 template <bool INV> struct Bfly<5, INV> {
-  __device__ static void run(double2* x) {
-    double2 a1 = cadd(x[1], x[4]), a2 = cadd(x[2], x[3]);
-    double2 b1 = csub(x[1], x[4]), b2 = csub(x[2], x[3]);
-    double2 x0 = x[0];
-    double2 r1 = make_double2(x0.x + C1_5 * a1.x + C2_5 * a2.x, x0.y + C1_5 * a1.y + C2_5 * a2.y);
-    double2 r2 = make_double2(x0.x + C2_5 * a1.x + C1_5 * a2.x, x0.y + C2_5 * a1.y + C1_5 * a2.y);
-    double2 i1 = make_double2(S1_5 * b1.x + S2_5 * b2.x, S1_5 * b1.y + S2_5 * b2.y);
-    double2 i2 = make_double2(S2_5 * b1.x - S1_5 * b2.x, S2_5 * b1.y - S1_5 * b2.y);
+  template <class C> __device__ static void run(C* x) {
+    using R = typename Cx<C>::R;
+    const R c1 = (R)C1_5, c2 = (R)C2_5, s1 = (R)S1_5, s2 = (R)S2_5;
+    C a1 = cadd(x[1], x[4]), a2 = cadd(x[2], x[3]);
+    C b1 = csub(x[1], x[4]), b2 = csub(x[2], x[3]);
+    C x0 = x[0];
+    C r1 = Cx<C>::mk(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+    C r2 = Cx<C>::mk(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+    C i1 = Cx<C>::mk(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+    C i2 = Cx<C>::mk(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
     // fwd: y1 = r1 - i i1, y4 = r1 + i i1, y2 = r2 - i i2, y3 = r2 + i i2
-    double2 j1 = mul_mi<INV>(i1), j2 = mul_mi<INV>(i2);
+    C j1 = mul_mi<INV>(i1), j2 = mul_mi<INV>(i2);
     x[0] = cadd(x0, cadd(a1, a2));
     x[1] = cadd(r1, j1);
     x[4] = csub(r1, j1);
@@ -498,8 +527,11 @@ struct PassGeom {
   }
 };
 
-template <class G, bool INV, class ORD, int s>
-__device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2* __restrict__ tw) {
+// TWF: every twiddle power from the (FP64) table, rounded once to the
+// register type -- the FP32-arithmetic mode's table of exactly rounded FP32
+// twiddles; otherwise the powers that are not a power of two are products.
+template <class G, bool INV, class ORD, int s, bool TWF, class C>
+__device__ __forceinline__ void compute_stage(C (&v)[G::E], const double2* __restrict__ tw) {
   constexpr int N = G::NN;
   constexpr int r = ORD::r(s), p = ORD::p(s);
   constexpr int E = G::E;
@@ -507,32 +539,32 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2*
   for (int u = 0; u < E / r; ++u) {
     int b, i;
     G::template map<r>(u, b, i);
-    double2* x = &v[u * r];
+    C* x = &v[u * r];
     if constexpr (p > 1) {
       // input m is multiplied by w^m, w = exp(sign 2 pi i k / (p r)) = W[k N/(p r)].
       // w^1, w^2, w^4, w^8 come from the table (exactly rounded); every other
       // power is the product of its highest power-of-two part and the rest.
       const int k = i % p;
       constexpr int step = N / (p * r);
-      double2 w[r];
-#if SSF_TW_FULL
+      C w[r];
+      if constexpr (TWF) {
 #pragma unroll
-      for (int m = 1; m < r; ++m) {
-        w[m] = tw[m * k * step];
-        if constexpr (INV) w[m].y = -w[m].y;
-      }
-#else
+        for (int m = 1; m < r; ++m) {
+          w[m] = to_c<C>(tw[m * k * step]);
+          if constexpr (INV) w[m].y = -w[m].y;
+        }
+      } else {
 #pragma unroll
-      for (int m = 1; m < r; m <<= 1) {
-        w[m] = tw[m * k * step];
-        if constexpr (INV) w[m].y = -w[m].y;
-      }
+        for (int m = 1; m < r; m <<= 1) {
+          w[m] = to_c<C>(tw[m * k * step]);
+          if constexpr (INV) w[m].y = -w[m].y;
+        }
 #pragma unroll
-      for (int m = 3; m < r; ++m) {
-        const int hp = 1 << (31 - __builtin_clz(m));
-        if (hp != m) w[m] = cmul(w[hp], w[m - hp]);
+        for (int m = 3; m < r; ++m) {
+          const int hp = 1 << (31 - __builtin_clz(m));
+          if (hp != m) w[m] = cmul(w[hp], w[m - hp]);
+        }
       }
-#endif
 #pragma unroll
       for (int m = 1; m < r; ++m) x[m] = cmul(x[m], w[m]);
     }
@@ -552,8 +584,9 @@ __device__ __forceinline__ void compute_stage(double2 (&v)[G::E], const double2*
 //
 // XB: 0 = FP64, one buffer; 1 = FP32, two alternating buffers; 2 = FP32, one
 // buffer (a barrier after the reads, as FP64).
-template <class G, class ORD, int s, int XB>
-__device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds, int& xp) {
+template <class G, class ORD, int s, int XB, class C>
+__device__ __forceinline__ void exchange(C (&v)[G::E], double2* lds, int& xp) {
+  using R = typename Cx<C>::R;
   constexpr int N = G::NN;
   constexpr int r1 = ORD::r(s - 1), p1 = ORD::p(s - 1);
   constexpr int r2 = ORD::r(s);
@@ -568,9 +601,9 @@ __device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds, int& 
     const int j = (i - k) * r1 + k;
 #pragma unroll
     for (int q = 0; q < r1; ++q) {
-      const double2 w = v[u * r1 + q];
+      const C w = v[u * r1 + q];
       if constexpr (X32) l32[G::lidx(b, j + q * p1)] = make_float2((float)w.x, (float)w.y);
-      else lds[G::lidx(b, j + q * p1)] = w;
+      else lds[G::lidx(b, j + q * p1)] = to_d(w);
     }
   }
   lds_sync<G::WAVELOCAL>();
@@ -582,9 +615,9 @@ __device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds, int& 
     for (int m = 0; m < r2; ++m) {
       if constexpr (X32) {
         const float2 w = l32[G::lidx(b, i + m * (N / r2))];
-        v[u * r2 + m] = make_double2((double)w.x, (double)w.y);
+        v[u * r2 + m] = Cx<C>::mk((R)w.x, (R)w.y);
       } else {
-        v[u * r2 + m] = lds[G::lidx(b, i + m * (N / r2))];
+        v[u * r2 + m] = to_c<C>(lds[G::lidx(b, i + m * (N / r2))]);
       }
     }
   }
@@ -594,27 +627,27 @@ __device__ __forceinline__ void exchange(double2 (&v)[G::E], double2* lds, int& 
 
 // All stages of one transform direction; v holds the inputs of stage 0 on
 // entry and the outputs of the last stage on exit.
-template <class G, bool INV, bool REV, int XB = 0>
-__device__ __forceinline__ void transform(double2 (&v)[G::E], double2* lds, const double2* __restrict__ tw, int& xp) {
+template <class G, bool INV, bool REV, int XB, bool TWF, class C>
+__device__ __forceinline__ void transform(C (&v)[G::E], double2* lds, const double2* __restrict__ tw, int& xp) {
   using ORD = Order<Plan<G::NN>, REV>;
   constexpr int NS = Plan<G::NN>::S;
   static_assert(NS <= 5, "at most 5 stages");
-  compute_stage<G, INV, ORD, 0>(v, tw);
+  compute_stage<G, INV, ORD, 0, TWF>(v, tw);
   if constexpr (NS > 1) {
     exchange<G, ORD, 1, XB>(v, lds, xp);
-    compute_stage<G, INV, ORD, 1>(v, tw);
+    compute_stage<G, INV, ORD, 1, TWF>(v, tw);
   }
   if constexpr (NS > 2) {
     exchange<G, ORD, 2, XB>(v, lds, xp);
-    compute_stage<G, INV, ORD, 2>(v, tw);
+    compute_stage<G, INV, ORD, 2, TWF>(v, tw);
   }
   if constexpr (NS > 3) {
     exchange<G, ORD, 3, XB>(v, lds, xp);
-    compute_stage<G, INV, ORD, 3>(v, tw);
+    compute_stage<G, INV, ORD, 3, TWF>(v, tw);
   }
   if constexpr (NS > 4) {
     exchange<G, ORD, 4, XB>(v, lds, xp);
-    compute_stage<G, INV, ORD, 4>(v, tw);
+    compute_stage<G, INV, ORD, 4, TWF>(v, tw);
   }
 }
 
@@ -703,8 +736,8 @@ __device__ __forceinline__ void potentials(const PassArgs& a, const double* sA, 
 
 // acc[g] += sum over the thread's values of dV/dxc_g Im(conj(lambda) psi),
 // dV/dxc_g = -D_g(x, z) B_g(y); psi is read from a.aux at the same offset.
-template <class G, int r, typename S>
-__device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 (&lam)[G::E], const Pen<G, r>& p,
+template <class G, int r, typename S, class C>
+__device__ __forceinline__ void adj_accumulate(const PassArgs& a, const C (&lam)[G::E], const Pen<G, r>& p,
                                                int z, double* acc) {
   constexpr int N = G::NN, U = Pen<G, r>::U;
   const S* __restrict__ aux = (const S*)a.aux;
@@ -718,7 +751,7 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 
 #pragma unroll
     for (int m = 0; m < r; ++m) {
       const int x = p.i[u] + m * (N / r);
-      const double2 l = lam[u * r + m];
+      const double2 l = to_d(lam[u * r + m]);
       const double2 w = ld2(aux + p.off[u] + x);
       const double im = l.x * w.y - l.y * w.x;  // Im(conj(lambda) psi)
       acc[0] -= D[x] * b0 * im;
@@ -762,10 +795,18 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const double2 
 //
 // Variant 2 kernels are built for four waves per SIMD (at most 128 VGPRs),
 // so that two of their half-size workgroups fit a CU.
+//
+// F32M (complex64 storage only): FP32 arithmetic in registers -- butterflies,
+// twiddle products and exchanges in FP32 with every twiddle power an exactly
+// rounded FP32 value of the FP64 table; the phase arguments, the phase and
+// kinetic factors themselves and every reduction stay FP64, each factor
+// rounded to FP32 once before it multiplies the field.
 template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH,
-          bool VT = false, int SV = 0>
+          bool VT = false, int SV = 0, bool F32M = false>
 __global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM), SV == 2 ? 4 : 1)
 pass_kernel(PassArgs a) {
+  static_assert(!F32M || sizeof(S) == 8, "FP32 arithmetic only with complex64 storage");
+  using C = typename std::conditional<F32M, float2, double2>::type;
   using G = PassGeom<S, N, PX, PO, CONTIG, EM>;
   using PL = Plan<N>;
   constexpr int E = G::E, WG = G::WG;
@@ -780,13 +821,16 @@ pass_kernel(PassArgs a) {
   // buffer (half the bytes); fused passes otherwise through two alternating
   // FP32 buffers (the bytes of one FP64 buffer); everything else FP64
   constexpr bool C64S = !CONTIG && sizeof(S) == 8 && PL::S > 1;
-  constexpr int XB = (C64S && SV == 2) ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0);
+  constexpr int XB = F32M ? ((C64S && FUSED && SV != 2 && SSF_X32) ? 1 : 2)
+                          : ((C64S && SV == 2) ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0));
   constexpr bool PF = SV != 2;                                     // register prefetch of the next tile
   int xpar = 0;
   __shared__ double2 lds[XB == 2 ? (G::LDS + 1) / 2 : G::LDS];
   // Power-of-two plans read twiddle powers W^t only for t < N/2 (the
   // products of lower powers are formed in registers), so half the table.
-  constexpr int TWN = (!SSF_TW_FULL && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N;
+  // (FP32 arithmetic reads every power from the table, so all of it.)
+  constexpr bool TWF = SSF_TW_FULL || F32M;
+  constexpr int TWN = (!TWF && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N;
   __shared__ double2 s_tw[TWN];
   __shared__ double2 s_kz[KZ ? N : 1];
   // Lean fused x pass whose waves own one row each (64 E = N): the guide
@@ -902,9 +946,10 @@ pass_kernel(PassArgs a) {
       }
     }
     if (!prefetch) load_tile(tg);
-    double2 v[E];
+    C v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = make_double2((double)raw[e].x, (double)raw[e].y);
+    for (int e = 0; e < E; ++e)
+      v[e] = Cx<C>::mk((typename Cx<C>::R)raw[e].x, (typename Cx<C>::R)raw[e].y);
     double2 kxy = make_double2(1.0, 0.0);
     if constexpr (KZ) kxy = cmul(kx_n, ky_n);
     double vcur[VT ? E : 1];
@@ -932,12 +977,12 @@ pass_kernel(PassArgs a) {
           double V[E];
           potentials<G, r0>(a, s_A, s_dyn, vt_k, p, V);
 #pragma unroll
-          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpre, a.imag));
+          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], to_c<C>(phase_factor<LOWP>(V[e] * a.cpre, a.imag)));
         }
       }
     }
 
-    transform<G, INV1, false, XB>(v, lds, s_tw, xpar);
+    transform<G, INV1, false, XB, TWF>(v, lds, s_tw, xpar);
 
     if constexpr (FUSED) {
       // outputs of the last stage sit at n = i + q N / rm
@@ -981,13 +1026,13 @@ pass_kernel(PassArgs a) {
           if constexpr (LEAN) {
             if (a.small_phase == 2) {
 #pragma unroll
-              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_tiny<LOWP>(V[e] * a.cmid));
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], to_c<C>(phase_tiny<LOWP>(V[e] * a.cmid)));
             } else if (a.small_phase == 1) {
 #pragma unroll
-              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_small<LOWP>(V[e] * a.cmid));
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], to_c<C>(phase_small<LOWP>(V[e] * a.cmid)));
             } else {
 #pragma unroll
-              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_rt<LOWP>(V[e] * a.cmid));
+              for (int e = 0; e < E; ++e) v[e] = cmul(v[e], to_c<C>(phase_rt<LOWP>(V[e] * a.cmid)));
             }
           } else if (a.mid == MID_VNORM) {
             // end of one step (half-step factor), the norm of that step's
@@ -999,16 +1044,17 @@ pass_kernel(PassArgs a) {
 #pragma unroll
               for (int q = 0; q < rm; ++q) {
                 const int e = u * rm + q;
-                const double2 f = phase_factor<LOWP>(V[e] * a.cmid, a.imag);
+                const C f = to_c<C>(phase_factor<LOWP>(V[e] * a.cmid, a.imag));
                 v[e] = cmul(v[e], f);
-                acc[0] += w * (v[e].x * v[e].x + v[e].y * v[e].y);
+                const double2 dv = to_d(v[e]);
+                acc[0] += w * (dv.x * dv.x + dv.y * dv.y);
                 v[e] = cmul(v[e], f);
               }
             }
           } else {
             potentials<G, rm>(a, s_A, s_dyn, vt_k, p, V);
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cmid, a.imag));
+            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], to_c<C>(phase_factor<LOWP>(V[e] * a.cmid, a.imag)));
           }
         }
       } else {
@@ -1018,11 +1064,12 @@ pass_kernel(PassArgs a) {
             int b, i;
             G::template map<rm>(u, b, i);
 #pragma unroll
-            for (int q = 0; q < rm; ++q) v[u * rm + q] = cmul(v[u * rm + q], cmul(kxy, s_kz[i + q * (N / rm)]));
+            for (int q = 0; q < rm; ++q)
+              v[u * rm + q] = cmul(v[u * rm + q], to_c<C>(cmul(kxy, s_kz[i + q * (N / rm)])));
           }
         }
       }
-      transform<G, !INV1, true, XB>(v, lds, s_tw, xpar);
+      transform<G, !INV1, true, XB, TWF>(v, lds, s_tw, xpar);
     }
 
     // ---- post ops + store (outputs of the last stage at n = i + q N / rl) ----
@@ -1036,7 +1083,7 @@ pass_kernel(PassArgs a) {
         if (a.post & (POST_VPHASE | POST_OBS)) potentials<G, r>(a, s_A, s_dyn, vt_k, p, V);
         if (a.post & POST_VPHASE) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], phase_factor<LOWP>(V[e] * a.cpost, a.imag));
+          for (int e = 0; e < E; ++e) v[e] = cmul(v[e], to_c<C>(phase_factor<LOWP>(V[e] * a.cpost, a.imag)));
         }
         if (a.post & POST_OBS) {
           const double zc = a.lo[2] + t1 * a.d[2];
@@ -1082,7 +1129,7 @@ pass_kernel(PassArgs a) {
               const int n = p.i[u] + q * (N / r);
               const int mz = 2 * n < a.nz ? n : n - a.nz;
               const double kz = a.kfac[2] * mz;
-              const double2 val = v[u * r + q];
+              const double2 val = to_d(v[u * r + q]);
               acc[0] += w * (kx * kx + ky * ky + kz * kz) * (val.x * val.x + val.y * val.y);
             }
           }
@@ -1158,8 +1205,8 @@ hipError_t launch_persistent(K kernel, int wg, size_t dyn, PassArgs a, dim3 tile
   return hipGetLastError();
 }
 
-// y/z passes of one tile variant (B: batched launch).
-template <typename S, int N, int DT, int VAR, bool B>
+// y/z passes of one tile variant (B: batched launch; F: FP32 arithmetic).
+template <typename S, int N, int DT, int VAR, bool B, bool F>
 hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t st) {
   constexpr int SX = Shape<N>::sx(DT, VAR), SO = Shape<N>::so(DT, VAR), SM = Shape<N>::sm(DT, VAR);
   constexpr int WGS = PassGeom<S, N, SX, SO, false, SM>::WG;
@@ -1167,18 +1214,18 @@ hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t s
   switch (kind) {
     case STRIDED_FWD:
       if (a.post == 0)
-        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true, B, false, VAR>, WGS, 0, a,
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, true, B, false, VAR, F>, WGS, 0, a,
                                  tiles, st, occ[0]);
       if constexpr (B) return hipErrorInvalidValue;
       else
-        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false, false, false, VAR>, WGS, 0,
-                                 a, tiles, st, occ[1]);
+        return launch_persistent(pass_kernel<S, N, SX, SO, false, false, false, SM, false, false, false, VAR, F>, WGS,
+                                 0, a, tiles, st, occ[1]);
     case STRIDED_INV:
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true, B, false, VAR>, WGS, 0, a, tiles,
-                               st, occ[2]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, false, true, SM, true, B, false, VAR, F>, WGS, 0, a,
+                               tiles, st, occ[2]);
     case STRIDED_FUSED:
-      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true, B, false, VAR>, WGS, 0, a, tiles,
-                               st, occ[3]);
+      return launch_persistent(pass_kernel<S, N, SX, SO, false, true, false, SM, true, B, false, VAR, F>, WGS, 0, a,
+                               tiles, st, occ[3]);
     default:
       return hipErrorInvalidValue;
   }
@@ -1190,7 +1237,7 @@ hipError_t launch_strided(int kind, const PassArgs& a, dim3 tiles, hipStream_t s
 // serve every strided pass without a reduction.  Batched launches (B) exist
 // for the passes of a real-time step: x forward with a pre phase, x inverse
 // with a post phase, the lean fused x pass and the lean y/z passes.
-template <typename S, int N, int DT, bool B>
+template <typename S, int N, int DT, bool B, bool F>
 hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hipStream_t st) {
   constexpr int CR = Shape<N>::cr();
   constexpr int WGC = PassGeom<S, N, CR, 1, true, 1>::WG;
@@ -1203,36 +1250,41 @@ hipError_t launch_pass(int kind, int variant, const PassArgs& a, dim3 tiles, hip
   const bool lean_t = a.pre == 0 && a.post == 0 && !a.imag && a.vkind == V_TAB64 && a.mid == MID_VPHASE;
   switch (kind) {
     case CONTIG_FWD:
-      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, false, 1, false, B>, WGC, dync, a, tiles, st,
-                               occ[0]);
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, false, 1, false, B, false, 0, F>, WGC, dync, a,
+                               tiles, st, occ[0]);
     case CONTIG_INV:
-      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, true, 1, false, B>, WGC, dync, a, tiles, st,
-                               occ[1]);
+      return launch_persistent(pass_kernel<S, N, CR, 1, true, false, true, 1, false, B, false, 0, F>, WGC, dync, a,
+                               tiles, st, occ[1]);
     case CONTIG_FUSED:
       if (lean_x)
-        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B>, WGC, dyn_bsc, a, tiles, st,
-                                 occ[2]);
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B, false, 0, F>, WGC, dyn_bsc, a,
+                                 tiles, st, occ[2]);
       if (lean_t)
-        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B, true>, WGC, 0, a, tiles,
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, true, B, true, 0, F>, WGC, 0, a, tiles,
                                  st, occ[4]);
       if constexpr (B) return hipErrorInvalidValue;
       else
-        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false, false>, WGC, dync, a, tiles, st,
-                                 occ[3]);
+        return launch_persistent(pass_kernel<S, N, CR, 1, true, true, true, 1, false, false, false, 0, F>, WGC, dync, a,
+                                 tiles, st, occ[3]);
     default:
-      return variant == 2   ? launch_strided<S, N, DT, 2, B>(kind, a, tiles, st)
-             : variant == 1 ? launch_strided<S, N, DT, 1, B>(kind, a, tiles, st)
-                            : launch_strided<S, N, DT, 0, B>(kind, a, tiles, st);
+      return variant == 2   ? launch_strided<S, N, DT, 2, B, F>(kind, a, tiles, st)
+             : variant == 1 ? launch_strided<S, N, DT, 1, B, F>(kind, a, tiles, st)
+                            : launch_strided<S, N, DT, 0, B, F>(kind, a, tiles, st);
   }
 }
 
+// Kernel-type index: 0 = complex64 storage with FP64 arithmetic, 1 =
+// complex128, 2 = complex64 storage with FP32 arithmetic (single fields only).
 template <int N>
-hipError_t launch_any(int kind, int dt_index, int variant, const PassArgs& a, dim3 grid, hipStream_t st) {
-  if (a.ninst > 0)
-    return dt_index == 0 ? launch_pass<float2, N, 0, true>(kind, variant, a, grid, st)
-                         : launch_pass<double2, N, 1, true>(kind, variant, a, grid, st);
-  return dt_index == 0 ? launch_pass<float2, N, 0, false>(kind, variant, a, grid, st)
-                       : launch_pass<double2, N, 1, false>(kind, variant, a, grid, st);
+hipError_t launch_any(int kind, int kt_index, int variant, const PassArgs& a, dim3 grid, hipStream_t st) {
+  if (a.ninst > 0) {
+    if (kt_index == 2) return hipErrorInvalidValue;
+    return kt_index == 0 ? launch_pass<float2, N, 0, true, false>(kind, variant, a, grid, st)
+                         : launch_pass<double2, N, 1, true, false>(kind, variant, a, grid, st);
+  }
+  if (kt_index == 2) return launch_pass<float2, N, 0, false, true>(kind, variant, a, grid, st);
+  return kt_index == 0 ? launch_pass<float2, N, 0, false, false>(kind, variant, a, grid, st)
+                       : launch_pass<double2, N, 1, false, false>(kind, variant, a, grid, st);
 }
 
 template <int N, int DT, int VAR>

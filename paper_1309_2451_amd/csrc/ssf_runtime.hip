@@ -384,6 +384,7 @@ struct ssf_handle {
   double dv = 1.0;
   int dtype = SSF_C128;
   int dti = 1;                         // 0 = complex64, 1 = complex128
+  int kti = 1;                         // kernels: dti, or 2 = complex64 storage with FP32 arithmetic
   size_t esize = 16;
   long long npts = 1;
   const KernelSet* ks[3] = {nullptr, nullptr, nullptr};
@@ -548,7 +549,7 @@ ssf_status launch(ssf_handle* h, int kind, int axis, const PassArgs& a) {
     ++used;
     HIP_TRY(hipEventRecord(e0, h->stream));
   }
-  hipError_t e = h->ks[axis]->launch(kind, h->dti, h->var[axis], a, g, h->stream);
+  hipError_t e = h->ks[axis]->launch(kind, h->kti, h->var[axis], a, g, h->stream);
   if (e != hipSuccess) return fail(SSF_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
   if (h->timing) HIP_TRY(hipEventRecord(e1, h->stream));
   return SSF_OK;
@@ -707,6 +708,7 @@ ssf_status ssf_create(const ssf_grid_desc* grid, int32_t dtype, void* hip_stream
   h->stream = (hipStream_t)hip_stream;
   h->dtype = dtype;
   h->dti = dtype == SSF_C64 ? 0 : 1;
+  h->kti = h->dti;
   h->esize = dtype == SSF_C64 ? 8 : 16;
   h->npts = 1;
   for (int a = 0; a < 3; ++a) {
@@ -871,6 +873,15 @@ ssf_status ssf_tune(ssf_handle* h, int32_t reps, int32_t* choice_out, double* us
 ssf_status ssf_set_fusion(ssf_handle* h, int32_t fuse_steps) {
   SSF_TRY(check_handle(h));
   h->fuse = fuse_steps ? 1 : 0;
+  return SSF_OK;
+}
+
+ssf_status ssf_set_arithmetic(ssf_handle* h, int32_t arith) {
+  SSF_TRY(check_handle(h));
+  if (arith != SSF_ARITH_F64 && arith != SSF_ARITH_F32) return fail(SSF_E_INVALID, "unknown arithmetic mode");
+  if (arith == SSF_ARITH_F32 && h->dti != 0)
+    return fail(SSF_E_INVALID, "FP32 arithmetic needs complex64 storage");
+  h->kti = arith == SSF_ARITH_F32 ? 2 : h->dti;
   return SSF_OK;
 }
 

@@ -130,6 +130,43 @@ def test_step_random_c64_vs_oracle(shape):
     s.close()
 
 
+@pytest.mark.parametrize("shape", [(20, 12, 40), (12, 8, 96), (8, 16, 512)])
+def test_fp32_arithmetic_mode_vs_oracle(shape):
+    """Complex64 storage with FP32 bulk arithmetic (ssf_set_arithmetic):
+    transforms and steps against the oracle within FP32 rounding over the
+    transform depth, and different from (less exact than) the FP64-arithmetic
+    mode on the same input."""
+    say("fp32 arithmetic", shape)
+    g, psi0, V = _random_case(shape, 8)
+    psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    dt, n = 0.013, 50
+    t64 = to_dev(psi0, s)
+    s.step(t64, n, dt)
+    s.set_arithmetic("f32")
+    for axis in (0, 1, 2):
+        t = to_dev(psi0, s)
+        s.fft(t, axes=(axis,))
+        err = rel(host(t), oracle.fft_axis(psi0, axis, -1))
+        assert err < 6e-8 * 3 * np.log2(max(g.n[axis], 2)) + 1e-7, (axis, err)
+    t = to_dev(psi0, s)
+    s.step(t, n, dt)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, dt, n)
+    err32, err64 = rel(host(t), ref), rel(host(t64), ref)
+    say("fp32 arithmetic rel L2 %.3e, fp64 arithmetic %.3e" % (err32, err64))
+    # 50 steps x 4-5 passes, each with a few FP32 roundings per transform stage
+    assert err32 < 2e-5
+    assert rel(host(t), host(t64)) > 1e-9
+    with pytest.raises(ssf.SSFError):
+        ssf.Solver(g.n, g.lo, g.hi, "c128").set_arithmetic("f32")
+    s.set_arithmetic("f64")
+    t = to_dev(psi0, s)
+    s.step(t, n, dt)
+    assert torch.equal(t, t64)
+    s.close()
+
+
 def test_config1_harmonic_c128():
     c = synth.config1()
     g = c["grid"]
