@@ -570,8 +570,12 @@ def section_obs(torch, ssf, device, n, steps, obs_every, imag_steps):
     import numpy as np
     import synth
     out = {}
-    for label, intuitive in (("counter_intuitive", False), ("intuitive", True)):
-        cfg = synth.config2(n, intuitive=intuitive)
+    # the workload's guides (they barely couple), then guides that couple
+    # (shallower, wider, closer), where the two orders differ in outcome
+    coupled = dict(v0=20.0, sigma=0.7, d0=2.0, delta=0.6)
+    for label, intuitive, kw in (("counter_intuitive", False, {}), ("intuitive", True, {}),
+                                 ("coupled_counter_intuitive", False, coupled), ("coupled_intuitive", True, coupled)):
+        cfg = synth.config2(n, intuitive=intuitive, **kw)
         cfg["imag_steps"] = imag_steps if imag_steps is not None else cfg["imag_steps"]
         g, gd = cfg["grid"], cfg["guides"]
         log("obs: %s order, midline partitions, %d steps" % (label, steps))
@@ -614,6 +618,19 @@ def section_obs(torch, ssf, device, n, steps, obs_every, imag_steps):
         out[label]["density_mean_x"] = float(np.sum(r * x[None, :]) / np.sum(r))
         out[label]["density_total"] = float(np.sum(r) * g.spacing(0) * g.spacing(2))
         s.close()
+        if kw:
+            # complex64 against complex128 where the transfer happens
+            out[label]["guides"] = kw
+            s = ssf.Solver(g.n, g.lo, g.hi, "c128", device=device)
+            s.set_guides(gd.v0, gd.sigma, gd.xc)
+            s.set_partition_z(xl, xh)
+            p128 = psi0.contiguous().clone()
+            r128 = s.step(p128, steps, cfg["dt"], obs_every=steps)
+            s.close()
+            out[label]["c64_vs_c128_rel_l2"] = rel_l2(torch, psi, p128)
+            out[label]["p3_c128"] = float(r128[-1]["pop"][2])
+            out[label]["p3_abs_err_c64"] = abs(float(rec[-1]["pop"][2]) - float(r128[-1]["pop"][2]))
+            del p128
         del psi, psi0
         torch.cuda.empty_cache()
     return out

@@ -204,6 +204,15 @@ ssf_status ssf_set_arithmetic(ssf_handle* h, int32_t arith);
  * entries).  Synchronises the stream.  ssf_set_tiles / ssf_get_tiles set and
  * read the choice (e.g. from a cache). */
 #define SSF_TILE_VARIANTS 3
+/* The tuner with a cache file: if cache_path (a text file, created if
+ * missing) holds a choice for this device architecture, grid, storage type
+ * and arithmetic, apply it without timing anything (*hit = 1); otherwise run
+ * ssf_tune(h, reps, ...), apply its choice and append a line
+ * "ssf-tiles-v1 <arch> <Nx>x<Ny>x<Nz> <c64|c128> <f64|f32> variants<V> | <y> <z>"
+ * (*hit = 0).  choice_out[3] and hit may be NULL.  Lines that do not parse
+ * are ignored; the last matching line wins.  Errors: INVALID (empty path,
+ * reps < 1, unwritable file), and those of ssf_tune. */
+ssf_status ssf_tune_cached(ssf_handle* h, int32_t reps, const char* cache_path, int32_t* choice_out, int32_t* hit);
 ssf_status ssf_tune(ssf_handle* h, int32_t reps, int32_t* choice_out, double* us_out);
 ssf_status ssf_set_tiles(ssf_handle* h, const int32_t* choice);
 ssf_status ssf_get_tiles(ssf_handle* h, int32_t* choice);

@@ -224,6 +224,15 @@ class Solver:
         _ssf.call("ssf_tune", self.h, int(reps), ctypes.c_void_p(ch.ctypes.data), ctypes.c_void_p(us.ctypes.data))
         return ch.tolist(), {(a, v): float(us[a * nv + v]) for a in (1, 2) for v in range(nv)}
 
+    def tune_cached(self, cache_path, reps=5):
+        """The tuner through a cache file (ssf_tune_cached): (choice[3], hit)."""
+        self._sync_stream()
+        ch = np.zeros(3, dtype=np.int32)
+        hit = np.zeros(1, dtype=np.int32)
+        _ssf.call("ssf_tune_cached", self.h, int(reps), str(cache_path).encode(), ctypes.c_void_p(ch.ctypes.data),
+                  ctypes.c_void_p(hit.ctypes.data))
+        return ch.tolist(), bool(hit[0])
+
     def set_tiles(self, choice):
         ch = np.ascontiguousarray(choice, dtype=np.int32)
         _ssf.call("ssf_set_tiles", self.h, ctypes.c_void_p(ch.ctypes.data))

@@ -42,7 +42,7 @@ EXPORTS = (
     "ssf_adjoint_segment", "ssf_profile_grad", "ssf_batch_create", "ssf_batch_run", "ssf_batch_tune",
     "ssf_batch_info", "ssf_batch_set_stream", "ssf_batch_destroy", "ssf_bspline_basis", "ssf_bspline_eval", "ssf_status_string", "ssf_last_error",
     "ssf_step_noalloc", "ssf_noalloc_scratch_bytes", "ssf_noalloc_scratch_need",
-    "ssf_chip_potential", "ssf_batch_create_tables", "ssf_set_arithmetic",
+    "ssf_chip_potential", "ssf_batch_create_tables", "ssf_set_arithmetic", "ssf_tune_cached",
 )
 
 
@@ -114,6 +114,7 @@ def load():
         "ssf_set_arithmetic": ([hp, i32], i32),
         "ssf_set_timing": ([hp, i32], i32),
         "ssf_tune": ([hp, i32, vp, vp], i32),
+        "ssf_tune_cached": ([hp, i32, ctypes.c_char_p, vp, vp], i32),
         "ssf_set_tiles": ([hp, vp], i32),
         "ssf_get_tiles": ([hp, vp], i32),
         "ssf_timing_read": ([hp, vp, vp], i32),

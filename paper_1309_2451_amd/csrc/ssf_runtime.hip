@@ -15,7 +15,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -867,6 +869,75 @@ ssf_status ssf_tune(ssf_handle* h, int32_t reps, int32_t* choice_out, double* us
   if (st != SSF_OK) { h->var[1] = h->var[2] = 0; return st; }
   if (choice_out)
     for (int a = 0; a < 3; ++a) choice_out[a] = h->var[a];
+  return SSF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Key of a tile choice in a tuning cache: the device architecture, the grid,
+// the storage type and the arithmetic, and the number of tile variants the
+// library has (a library with other variants starts over).
+ssf_status tune_key(const ssf_handle* h, std::string* key) {
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, h->device));
+  std::ostringstream k;
+  std::string arch(prop.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  k << "ssf-tiles-v1 " << arch << " " << h->n[0] << "x" << h->n[1] << "x" << h->n[2] << " "
+    << (h->dti == 0 ? "c64" : "c128") << " " << (h->kti == 2 ? "f32" : "f64") << " variants" << SSF_TILE_VARIANTS;
+  *key = k.str();
+  return SSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssf_status ssf_tune_cached(ssf_handle* h, int32_t reps, const char* cache_path, int32_t* choice_out, int32_t* hit) {
+  SSF_TRY(check_handle(h));
+  if (!cache_path || !*cache_path) return fail(SSF_E_INVALID, "cache path is empty");
+  if (reps < 1) return fail(SSF_E_INVALID, "reps must be >= 1");
+  std::string key;
+  SSF_TRY(tune_key(h, &key));
+  // a line is: <key> | <variant y> <variant z>; the last line with the key wins
+  int found[2] = {-1, -1};
+  {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (in && std::getline(in, line)) {
+      const size_t bar = line.find(" | ");
+      if (bar == std::string::npos || line.compare(0, bar, key) != 0 || bar != key.size()) continue;
+      std::istringstream rest(line.substr(bar + 3));
+      int vy = -1, vz = -1;
+      if (rest >> vy >> vz && vy >= 0 && vy < SSF_TILE_VARIANTS && vz >= 0 && vz < SSF_TILE_VARIANTS) {
+        found[0] = vy;
+        found[1] = vz;
+      }
+    }
+  }
+  if (found[0] >= 0) {
+    h->var[1] = found[0];
+    h->var[2] = found[1];
+    if (choice_out)
+      for (int a = 0; a < 3; ++a) choice_out[a] = h->var[a];
+    if (hit) *hit = 1;
+    return SSF_OK;
+  }
+  int32_t choice[3] = {0, 0, 0};
+  SSF_TRY(ssf_tune(h, reps, choice, nullptr));
+  std::ofstream out(cache_path, std::ios::app);
+  if (!out) return fail(SSF_E_INVALID, std::string("cannot append to the tuning cache ") + cache_path);
+  std::ostringstream line;
+  line << key << " | " << choice[1] << " " << choice[2] << "\n";
+  out << line.str();
+  out.flush();
+  if (!out) return fail(SSF_E_INVALID, std::string("cannot write the tuning cache ") + cache_path);
+  if (choice_out)
+    for (int a = 0; a < 3; ++a) choice_out[a] = choice[a];
+  if (hit) *hit = 0;
   return SSF_OK;
 }
 

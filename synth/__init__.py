@@ -163,12 +163,15 @@ def config1():
     return dict(name="harmonic 64^3", grid=g, psi0=psi0, V=V, dt=0.005, steps=200)
 
 
-def config2(n=(256, 256, 512), intuitive=False):
+def config2(n=(256, 256, 512), intuitive=False, v0=40.0, sigma=0.6, d0=3.0, delta=1.2):
     """Three-guide CTAP, 256 x 256 x 512 on [-8,8)^2 x [-64,64), 10^4 real steps
     at dt = 0.002, z packet at z0 = -30 (width 4) moving with k_z = 3.
-    intuitive=True swaps the bumps (the 1-2 pair approaches first)."""
+    intuitive=True swaps the bumps (the 1-2 pair approaches first).  The guide
+    parameters default to the workload's (v0 = 40, sigma = 0.6, d0 = 3,
+    delta = 1.2), where the wells barely couple."""
     g = Grid(tuple(n), (-8.0, -8.0, -64.0), (8.0, 8.0, 64.0))
-    guides = ctap_guides(g, z1=-6.0, z3=6.0) if intuitive else ctap_guides(g)
+    kw = dict(v0=v0, sigma=sigma, d0=d0, delta=delta)
+    guides = ctap_guides(g, z1=-6.0, z3=6.0, **kw) if intuitive else ctap_guides(g, **kw)
     return dict(name="ctap %dx%dx%d" % tuple(n), grid=g, guides=guides, dt=0.002,
                 steps=10000, imag_steps=2000, z0=-30.0, zwidth=4.0, kz=3.0)
 

@@ -601,3 +601,38 @@ def test_gradient_workload_full_size_vs_oracle_adjoint():
     assert abs(float(F.detach()) - F_ref) < 1e-12
     assert np.max(np.abs(grad - grad_ref)) < 1e-9 * scale
     s.close()
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """ssf_tune_cached: a miss tunes and appends one line, a hit applies the
+    stored choice without tuning, other grids get their own lines, unparsable
+    lines are ignored and the last matching line wins."""
+    path = tmp_path / "tiles.txt"
+    g = synth.Grid((32, 24, 40), (-4.0, -3.0, -5.0), (4.0, 3.0, 5.0))
+    s = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    ch, hit = s.tune_cached(path, reps=2)
+    assert not hit and ch[0] == 0 and ch[1] in (0, 1, 2) and ch[2] in (0, 1, 2)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and " 32x24x40 c64 f64 " in lines[0]
+    s2 = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    ch2, hit2 = s2.tune_cached(path, reps=2)
+    assert hit2 and ch2 == ch and s2.get_tiles() == ch
+    g3 = synth.Grid((16, 24, 40), (-4.0, -3.0, -5.0), (4.0, 3.0, 5.0))
+    s3 = ssf.Solver(g3.n, g3.lo, g3.hi, "c128")
+    _, hit3 = s3.tune_cached(path, reps=2)
+    assert not hit3 and len(path.read_text().splitlines()) == 2
+    other = [v for v in (0, 1, 2) if v != ch[2]][0]
+    with open(path, "a") as f:
+        f.write("garbage line\n")
+        f.write(lines[0].split(" | ")[0] + " | %d %d\n" % (ch[1], other))
+    s4 = ssf.Solver(g.n, g.lo, g.hi, "c64")
+    ch4, hit4 = s4.tune_cached(path, reps=2)
+    assert hit4 and ch4 == [0, ch[1], other]
+    # the stored choice gives the oracle's transform
+    rng = np.random.default_rng(3)
+    x = c64_round(rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape))
+    t = to_dev(x, s4)
+    s4.fft(t, axes=(2,))
+    assert rel(host(t), oracle.fft_axis(x, 2, -1)) < 2e-7
+    for h in (s, s2, s3, s4):
+        h.close()
