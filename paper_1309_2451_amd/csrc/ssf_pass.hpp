@@ -88,7 +88,7 @@ template <class PL, bool REV> struct Order {
 #define SSF_TILE_INTERLEAVE 1  // y/z workgroups take every gridDim-th tile (0: a contiguous range)
 #endif
 #ifndef SSF_X32
-#define SSF_X32 1              // FP32 double-buffered LDS exchanges in fused strided passes (complex64)
+#define SSF_X32 1              // FP32 LDS exchanges in the fused passes of complex64 fields
 #endif
 
 // Tile shapes.  LDS holds P pencils of N FP64 complex values.
@@ -817,19 +817,23 @@ pass_kernel(PassArgs a) {
   constexpr int UM = E / rm;
   constexpr bool LOWP = sizeof(S) == 8;                            // complex64 storage: shorter phase series
 
-  // LDS exchanges of complex64 strided passes: variant 2 through one FP32
-  // buffer (half the bytes); fused passes otherwise through two alternating
-  // FP32 buffers (the bytes of one FP64 buffer); everything else FP64
+  // LDS exchanges of complex64 passes: strided variant 2 and the lean fused
+  // x pass through one FP32 buffer (half the bytes); other fused strided
+  // passes through two alternating FP32 buffers (the bytes of one FP64
+  // buffer); everything else FP64
   constexpr bool C64S = !CONTIG && sizeof(S) == 8 && PL::S > 1;
+  constexpr bool C64X = CONTIG && FUSED && LEAN && sizeof(S) == 8 && PL::S > 1 && SSF_X32;
   constexpr int XB = F32M ? ((C64S && FUSED && SV != 2 && SSF_X32) ? 1 : 2)
-                          : ((C64S && SV == 2) ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0));
+                          : ((C64S && SV == 2) || C64X ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0));
   constexpr bool PF = SV != 2;                                     // register prefetch of the next tile
   int xpar = 0;
   __shared__ double2 lds[XB == 2 ? (G::LDS + 1) / 2 : G::LDS];
   // Power-of-two plans read twiddle powers W^t only for t < N/2 (the
   // products of lower powers are formed in registers), so half the table.
-  // (FP32 arithmetic reads every power from the table, so all of it.)
-  constexpr bool TWF = SSF_TW_FULL || F32M;
+  // (FP32 arithmetic and the x passes read every power from the table, so
+  // all of it: in the x passes that trades four complex products per radix-8
+  // butterfly for four LDS reads, measured faster there and slower in y/z.)
+  constexpr bool TWF = SSF_TW_FULL || F32M || CONTIG;
   constexpr int TWN = (!TWF && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N;
   __shared__ double2 s_tw[TWN];
   __shared__ double2 s_kz[KZ ? N : 1];
