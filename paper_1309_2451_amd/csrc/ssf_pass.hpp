@@ -164,6 +164,22 @@ template <class C> __device__ __forceinline__ C csub(C a, C b) { return Cx<C>::m
 template <class C> __device__ __forceinline__ C cmul(C a, C b) {
   return Cx<C>::mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// x K for a butterfly constant K.  In FP32 the constant is split into two
+// FP32 terms and the product is rounded once from (nearly) the exact x K.  A
+// one-term FP32 constant would scale by the same 1 + (relative error of K) in
+// every butterfly of every step, a systematic drift of the norm (for sqrt(1/2),
+// -1.7e-8 on the odd outputs of each radix-8 butterfly).
+template <class R> __device__ __forceinline__ R kmul(R x, double K) {
+  if constexpr (sizeof(R) == 4) {
+    const float hi = (float)K, lo = (float)(K - (double)hi);
+    return __builtin_fmaf(x, hi, x * lo);
+  } else {
+    return x * K;
+  }
+}
+template <class C> __device__ __forceinline__ C kscale(C a, double K) {
+  return Cx<C>::mk(kmul(a.x, K), kmul(a.y, K));
+}
 template <class C> __device__ __forceinline__ C cscale(C a, double s) {
   const typename Cx<C>::R t = (typename Cx<C>::R)s;
   return Cx<C>::mk(a.x * t, a.y * t);
@@ -177,13 +193,13 @@ template <bool INV, class C> __device__ __forceinline__ C mul_mi(C a) {
 constexpr double SQRT1_2 = 0.70710678118654752440084436210485;
 template <bool INV, class C> __device__ __forceinline__ C mul_w8_1(C a) {
   // fwd: (1 - i)/sqrt2, inv: (1 + i)/sqrt2
-  const typename Cx<C>::R h = (typename Cx<C>::R)SQRT1_2;
-  return INV ? Cx<C>::mk((a.x - a.y) * h, (a.x + a.y) * h) : Cx<C>::mk((a.x + a.y) * h, (a.y - a.x) * h);
+  return INV ? Cx<C>::mk(kmul(a.x - a.y, SQRT1_2), kmul(a.x + a.y, SQRT1_2))
+             : Cx<C>::mk(kmul(a.x + a.y, SQRT1_2), kmul(a.y - a.x, SQRT1_2));
 }
 template <bool INV, class C> __device__ __forceinline__ C mul_w8_3(C a) {
   // fwd: (-1 - i)/sqrt2, inv: (-1 + i)/sqrt2
-  const typename Cx<C>::R h = (typename Cx<C>::R)SQRT1_2;
-  return INV ? Cx<C>::mk((-a.x - a.y) * h, (a.x - a.y) * h) : Cx<C>::mk((a.y - a.x) * h, (-a.x - a.y) * h);
+  return INV ? Cx<C>::mk(kmul(-a.x - a.y, SQRT1_2), kmul(a.x - a.y, SQRT1_2))
+             : Cx<C>::mk(kmul(a.y - a.x, SQRT1_2), kmul(-a.x - a.y, SQRT1_2));
 }
 
 // Storage conversions.  Field and table pointers may come from a batch
@@ -302,7 +318,7 @@ template <bool INV> struct Bfly<3, INV> {
     C s = csub(x[1], x[2]);
     C a = Cx<C>::mk(x[0].x - (R)0.5 * t.x, x[0].y - (R)0.5 * t.y);
     // fwd: y1 = a - i (sqrt3/2) s, y2 = a + i (sqrt3/2) s
-    C b = mul_mi<INV>(cscale(s, SIN_2PI_3));
+    C b = mul_mi<INV>(kscale(s, SIN_2PI_3));
     x[0] = cadd(x[0], t);
     x[1] = cadd(a, b);
     x[2] = csub(a, b);
@@ -315,15 +331,13 @@ constexpr double S1_5 = 0.95105651629515357211643933337938;   // sin(2 pi / 5)
 constexpr double S2_5 = 0.58778525229247312916870595463907;   // sin(4 pi / 5)
 template <bool INV> struct Bfly<5, INV> {
   template <class C> __device__ static void run(C* x) {
-    using R = typename Cx<C>::R;
-    const R c1 = (R)C1_5, c2 = (R)C2_5, s1 = (R)S1_5, s2 = (R)S2_5;
     C a1 = cadd(x[1], x[4]), a2 = cadd(x[2], x[3]);
     C b1 = csub(x[1], x[4]), b2 = csub(x[2], x[3]);
     C x0 = x[0];
-    C r1 = Cx<C>::mk(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
-    C r2 = Cx<C>::mk(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
-    C i1 = Cx<C>::mk(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
-    C i2 = Cx<C>::mk(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+    C r1 = Cx<C>::mk(x0.x + kmul(a1.x, C1_5) + kmul(a2.x, C2_5), x0.y + kmul(a1.y, C1_5) + kmul(a2.y, C2_5));
+    C r2 = Cx<C>::mk(x0.x + kmul(a1.x, C2_5) + kmul(a2.x, C1_5), x0.y + kmul(a1.y, C2_5) + kmul(a2.y, C1_5));
+    C i1 = Cx<C>::mk(kmul(b1.x, S1_5) + kmul(b2.x, S2_5), kmul(b1.y, S1_5) + kmul(b2.y, S2_5));
+    C i2 = Cx<C>::mk(kmul(b1.x, S2_5) - kmul(b2.x, S1_5), kmul(b1.y, S2_5) - kmul(b2.y, S1_5));
     // fwd: y1 = r1 - i i1, y4 = r1 + i i1, y2 = r2 - i i2, y3 = r2 + i i2
     C j1 = mul_mi<INV>(i1), j2 = mul_mi<INV>(i2);
     x[0] = cadd(x0, cadd(a1, a2));
@@ -921,7 +935,16 @@ pass_kernel(PassArgs a) {
                                                    (!ctap && a.vkind != V_NONE))));
 
   int plane = -1, binst = -1;
-  if (prefetch) load_tile(tbeg);
+  if (prefetch) {
+    load_tile(tbeg);
+    // x passes wait for the first tile here.  Otherwise the loop head merges
+    // this path (its loads the newest memory operations) with the back edge
+    // (prefetched loads, then the previous tile's stores), and the counter
+    // waits it derives for the prefetched registers also drain those stores
+    // before every tile.  (vmcnt(0), expcnt and lgkmcnt at their maxima.)
+    // The strided passes measured faster with the drain, so they keep it.
+    if constexpr (CONTIG) __builtin_amdgcn_s_waitcnt(0x0F70);
+  }
   for (int tg = tbeg; tg < tend; tg += tstep) {
     const int k = BATCH ? __builtin_amdgcn_readfirstlane(tg / tpi) : 0;
     const int t = tg - k * tpi;

@@ -496,6 +496,61 @@ def test_gradient_workload_copy_vs_oracle_adjoint(dtype):
     s.close()
 
 
+def test_gradient_where_the_guides_couple():
+    """The gradient workload's box with guides that couple (v0 = 20, sigma = 0.7,
+    d0 = 2, delta = 0.6; the packet crosses the coupling region and ends with
+    most of its population in the third guide), 48 x 48 x 128, 4000 steps:
+    the adjoint gradient against Richardson-extrapolated central differences
+    in complex128, and the complex64 gradient against the complex128 one."""
+    from paper_1309_2451_amd.fidelity import FidelityFn, FidelityProblem
+    g = synth.Grid((48, 48, 128), (-8.0, -8.0, -48.0), (8.0, 8.0, 48.0))
+    M, dt, n, every = 16, 0.004, 4000, 100
+    a, b = g.lo[2], g.hi[2]
+    zg = synth.greville(M, a, b)
+    prof = synth.ctap_profile(zg, 2.0, 0.6, 6.0, -6.0, 8.0)
+    rng = np.random.default_rng(23)
+    coeffs = np.stack([prof[0], prof[2]]) + 0.05 * rng.standard_normal((2, M))
+    nominal = synth.ctap_profile(g.axis(2), 2.0, 0.6, 6.0, -6.0, 8.0)
+    z0 = -24.0
+    iz = int(round((z0 - g.lo[2]) / g.spacing(2)))
+    psi0 = synth.gaussian_packet(g, centre=(nominal[0, iz], 0.0, z0), width=(0.5, 0.5, 3.0), k=(0.0, 0.0, 3.0))
+    out = {}
+    for dtype in ("c128", "c64"):
+        say("coupled gradient", dtype)
+        s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+        p0 = c64_round(psi0) if dtype == "c64" else psi0
+        prob = FidelityProblem(s, to_dev(p0, s), np.full(3, 20.0), np.full(3, 0.7), np.zeros(g.n[2]), M, (a, b),
+                               -1.0, 1.0, dt, n, every)
+        c = torch.tensor(coeffs, dtype=torch.float64, requires_grad=True)
+        F = FidelityFn.apply(c, prob)
+        F.backward()
+        out[dtype] = (float(F.detach()), c.grad.numpy().copy(), prob, s)
+    F128, g128, prob, s = out["c128"]
+    F64, g64 = out["c64"][0], out["c64"][1]
+    scale = np.max(np.abs(g128))
+    say("F c128 %.6f c64 %.6f, max|dF/dc| %.4e, c64 gradient error %.3e" % (F128, F64, scale,
+                                                                          np.max(np.abs(g64 - g128)) / scale))
+    assert F128 > 0.3                                   # most of the population transferred
+    assert abs(F64 - F128) < 1e-4 * F128
+    assert np.max(np.abs(g64 - g128)) < 1e-3 * scale
+    top = np.dstack(np.unravel_index(np.argsort(-np.abs(g128), axis=None)[:2], g128.shape))[0]
+
+    def central(k, m, h):
+        cp, cm = coeffs.copy(), coeffs.copy()
+        cp[k, m] += h
+        cm[k, m] -= h
+        return (prob.forward(cp) - prob.forward(cm)) / (2 * h)
+
+    h = 1e-3
+    for k, m in top:
+        d1, d2 = central(k, m, h), central(k, m, h / 2)
+        rich = (4.0 * d2 - d1) / 3.0
+        say("central differences (%d, %d): extrapolated %.8e, adjoint %.8e" % (k, m, rich, g128[k, m]))
+        assert abs(rich - g128[k, m]) <= 1e-5 * abs(g128[k, m]), (k, m, rich, g128[k, m])
+    for dtype in ("c128", "c64"):
+        out[dtype][3].close()
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_full_size_workload_vs_oracle(dtype):
     """The headline workload at its full size (256 x 256 x 512, three guides) in
