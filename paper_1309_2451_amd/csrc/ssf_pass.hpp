@@ -831,19 +831,19 @@ pass_kernel(PassArgs a) {
   constexpr int UM = E / rm;
   constexpr bool LOWP = sizeof(S) == 8;                            // complex64 storage: shorter phase series
 
-  // LDS exchanges of complex64 passes: strided variant 2 where it doubles
-  // the values per thread, and the lean fused x pass, through one FP32
-  // buffer (half the bytes); other fused strided passes through two
-  // alternating FP32 buffers (the bytes of one FP64 buffer); everything
-  // else FP64.  (Where variant 2 keeps the variant-0 values per thread, as
-  // for the 12- and 20-value plans, FP32 exchanges in its single-transform
-  // passes measured a steady loss of norm at 96 points, 2e-9 per step, and
-  // it exchanges like variant 0.)
+  // LDS exchanges of complex64 passes: strided variant 2 and the lean fused
+  // x pass through one FP32 buffer (half the bytes); other fused strided
+  // passes through two alternating FP32 buffers (the bytes of one FP64
+  // buffer); everything else FP64.  The single-transform passes of the
+  // 3 * 2^k-point plans exchange in FP64 in every variant: at 96
+  // points FP32 rounding at their stage boundaries lost norm steadily, 2e-9
+  // per step (the same with FP64 exchanges rounded to FP32 precision), where
+  // the fused passes and the other plans show no such loss.
   constexpr bool C64S = !CONTIG && sizeof(S) == 8 && PL::S > 1;
-  constexpr bool V2D = SV == 2 && EM == 2 * Shape<N>::sm0(0);
+  constexpr bool V2X = SV == 2 && (FUSED || N % 3 != 0);
   constexpr bool C64X = CONTIG && FUSED && LEAN && sizeof(S) == 8 && PL::S > 1 && SSF_X32;
   constexpr int XB = F32M ? ((C64S && FUSED && SV != 2 && SSF_X32) ? 1 : 2)
-                          : ((C64S && V2D) || C64X ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0));
+                          : ((C64S && V2X) || C64X ? 2 : ((C64S && FUSED && SSF_X32) ? 1 : 0));
   constexpr bool PF = SV != 2;                                     // register prefetch of the next tile
   int xpar = 0;
   __shared__ double2 lds[XB == 2 ? (G::LDS + 1) / 2 : G::LDS];

@@ -422,7 +422,7 @@ def test_complex64_norm_holds_for_every_tile_variant(n):
     """A sweep-size instance (n^3, complex64, dt = 0.004) over 500 steps with
     each y/z tile variant: the norm stays within 2e-7 of its start.  Storage
     rounding alone moves it by a few 1e-8; FP32 exchanges in the 96-point
-    single-transform passes once lost 1e-6 in 500 steps."""
+    single-transform passes lost 1e-6 in 500 steps."""
     say("complex64 norm, every tile variant", n)
     cfg = synth.config4(96)
     it = [i for i in cfg["instances"] if tuple(i["grid"].n) == (n, n, n)][0]
