@@ -44,6 +44,13 @@ Further sections (each can be skipped with --sections):
            midlines between the moving guides, in the counter-intuitive and
            the intuitive bump order: populations against time, rate, and the
            y-integrated x-z density of the final state (time per snapshot).
+  chip     the atom-chip workload (256 x 64 x 1024, 6Li): the potential from
+           the three wire paths, complex64 and complex128 steps with
+           populations against time, and a batch sweep of the middle-wire
+           current.
+  slab     one GPU's share of 512^3 complex64 over 8 GPUs: the x and y passes
+           on a 512 x 512 x 64 z-slab and the fused z pass on a 512 x 64 x 512
+           y-slab (measured), the all-to-all between them (modelled).
 """
 from __future__ import annotations
 
@@ -60,7 +67,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point split-step updates/s + HBM GB/s vs roofline, c64 vs c128 at ≤1e-4 L2"
-ALL_SECTIONS = ("c128", "accuracy", "cpu", "batch", "adjoint", "c3", "tvt", "obs", "chip")
+ALL_SECTIONS = ("c128", "accuracy", "cpu", "batch", "adjoint", "c3", "tvt", "obs", "chip", "slab")
 ACCURACY_STEPS = 10000
 
 
@@ -688,6 +695,55 @@ def section_c3(torch, ssf, device, steps=None, obs_every=100):
     return out
 
 
+def section_slab(torch, ssf, device, steps=200, gpus=8, link_gbs=153.0, links=7):
+    """One GPU's share of the 512^3 complex64 workload split over `gpus` GPUs:
+    z-slabs (512 x 512 x 512/gpus) for the x and y passes and y-slabs
+    (512 x 512/gpus x 512) for the fused z pass, each timed on a grid of that
+    shape (tuned tiles, per-pass HIP events over `steps` steady steps, the
+    guides restricted to the slab).  The all-to-all between the two layouts is
+    not run here (one GPU); its time is modelled from the bytes and the xGMI
+    link rate and reported apart from the measured pass times."""
+    import numpy as np
+    import synth
+    full = synth.config3()
+    fg, fgd = full["grid"], full["guides"]
+    m = fg.n[2] // gpus
+    out = {"workload": "one GPU's share of 512^3 complex64 over %d GPUs: z-slab %dx%dx%d (x, y passes), "
+                       "y-slab %dx%dx%d (fused z pass), %d steps each" % (gpus, fg.n[0], fg.n[1], m, fg.n[0], m,
+                                                                          fg.n[2], steps)}
+    # z-slab: the first m planes of the box
+    zg = synth.Grid((fg.n[0], fg.n[1], m), fg.lo, (fg.hi[0], fg.hi[1], fg.lo[2] + m * fg.spacing(2)))
+    zgd = synth.Guides(v0=fgd.v0, sigma=fgd.sigma, xc=np.ascontiguousarray(fgd.xc[:, :m]), x_lo=fgd.x_lo,
+                       x_hi=fgd.x_hi)
+    # y-slab: the first m rows in y, every z plane
+    yg = synth.Grid((fg.n[0], m, fg.n[2]), fg.lo, (fg.hi[0], fg.lo[1] + m * fg.spacing(1), fg.hi[2]))
+    res = {}
+    for name, g, gd in (("zslab", zg, zgd), ("yslab", yg, fgd)):
+        cfg = dict(grid=g, guides=gd, dt=full["dt"])
+        psi0 = torch.from_numpy(synth.gaussian_packet(g, centre=(gd.xc[0, 0], g.lo[1] + 0.5 * (g.hi[1] - g.lo[1]),
+                                                                 g.lo[2] + 0.5 * (g.hi[2] - g.lo[2])),
+                                                     width=(0.4, 0.4, 4.0), k=(0.0, 0.0, full["kz"]))).to(device)
+        log("slab: %s %dx%dx%d, %d steps" % (name, g.n[0], g.n[1], g.n[2], steps))
+        r = timed_run(torch, ssf, cfg, psi0, "c64", steps, 5, 100, device, window=steps)
+        res[name] = {"grid": list(g.n), "tiles": r["tune"]["choice"], "passes": pass_summary(r["window"])}
+        del psi0
+    zp, yp = res["zslab"]["passes"], res["yslab"]["passes"]
+    local_us = zp["x_inv_phase_fwd"]["avg_us"] + zp["yz_fwd"]["avg_us"] + zp["yz_inv"]["avg_us"] + \
+        yp["z_fwd_kin_inv"]["avg_us"]
+    share = fg.points // gpus
+    a2a_bytes = 2 * (gpus - 1) / gpus * share * 8                 # two all-to-alls per step
+    a2a_ms = a2a_bytes / (links * link_gbs * 1e9) * 1e3
+    out.update(res)
+    out["local_passes_us"] = {"x_fused": zp["x_inv_phase_fwd"]["avg_us"], "y_fwd": zp["yz_fwd"]["avg_us"],
+                              "y_inv": zp["yz_inv"]["avg_us"], "z_fused": yp["z_fwd_kin_inv"]["avg_us"]}
+    out["local_ms_per_step"] = local_us / 1e3
+    out["local_updates_per_s_per_gpu"] = share / (local_us * 1e-6)
+    out["local_algorithmic_frac"] = 4 * 2 * 8 * share / (local_us * 1e-6) / (HBM_PEAK_GBS * 1e9)
+    out["all_to_all_model"] = {"bytes_per_gpu_per_step": a2a_bytes, "ms_per_step": a2a_ms,
+                               "basis": "%d xGMI links x %.0f GB/s, not overlapped, not measured" % (links, link_gbs)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -888,6 +944,9 @@ def main():
         torch.cuda.empty_cache()
     if "chip" in sections:
         out["chip"] = section_chip(torch, ssf, device, steps=a.chip_steps, sweep_steps=a.chip_sweep_steps)
+        torch.cuda.empty_cache()
+    if "slab" in sections:
+        out["slab"] = section_slab(torch, ssf, device)
         torch.cuda.empty_cache()
     if "cpu" in sections:
         log("CPU oracle baseline")
