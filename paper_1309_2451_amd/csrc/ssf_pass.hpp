@@ -66,6 +66,7 @@ SSF_PLAN(640, 20, 2, 4, 4, 4, 5)
 #undef SSF_PLAN
 
 template <class PL, bool REV> struct Order {
+  static constexpr bool rev = REV;
   static constexpr int r(int s) { return REV ? PL::R[PL::S - 1 - s] : PL::R[s]; }
   static constexpr int p(int s) {
     int q = 1;
@@ -544,6 +545,9 @@ struct PassGeom {
 // TWF: every twiddle power from the (FP64) table, rounded once to the
 // register type -- the FP32-arithmetic mode's table of exactly rounded FP32
 // twiddles; otherwise the powers that are not a power of two are products.
+// The x passes read a stage-major copy of the table (stage_twiddles), one
+// block per radix order, so that the lanes of a read take consecutive
+// entries.
 template <class G, bool INV, class ORD, int s, bool TWF, class C>
 __device__ __forceinline__ void compute_stage(C (&v)[G::E], const double2* __restrict__ tw) {
   constexpr int N = G::NN;
@@ -561,7 +565,14 @@ __device__ __forceinline__ void compute_stage(C (&v)[G::E], const double2* __res
       const int k = i % p;
       constexpr int step = N / (p * r);
       C w[r];
-      if constexpr (TWF) {
+      if constexpr (TWF && G::CONTIGUOUS) {
+        const double2* ts = tw + (ORD::rev ? N : 0) + (p - ORD::p(1));
+#pragma unroll
+        for (int m = 1; m < r; ++m) {
+          w[m] = to_c<C>(ts[(m - 1) * p + k]);
+          if constexpr (INV) w[m].y = -w[m].y;
+        }
+      } else if constexpr (TWF) {
 #pragma unroll
         for (int m = 1; m < r; ++m) {
           w[m] = to_c<C>(tw[m * k * step]);
@@ -583,6 +594,21 @@ __device__ __forceinline__ void compute_stage(C (&v)[G::E], const double2* __res
       for (int m = 1; m < r; ++m) x[m] = cmul(x[m], w[m]);
     }
     Bfly<r, INV>::run(x);
+  }
+}
+
+// Stage-major twiddle table of one radix order: for every stage s >= 1 the
+// powers W^(m k N/(p r)), m = 1..r-1, k = 0..p-1, at (p_s - p_1) + (m-1) p + k,
+// so that the lanes of a read take consecutive entries.
+template <class ORD, int N>
+__device__ void stage_twiddles(double2* dst, const double2* __restrict__ tw) {
+  constexpr int S = Plan<N>::S;
+  for (int s = 1; s < S; ++s) {
+    const int p = ORD::p(s), r = ORD::r(s), off = p - ORD::p(1), step = N / (p * r);
+    for (int j = threadIdx.x; j < (r - 1) * p; j += blockDim.x) {
+      const int m = j / p + 1, k = j % p;
+      dst[off + j] = tw[m * k * step];
+    }
   }
 }
 
@@ -851,9 +877,11 @@ pass_kernel(PassArgs a) {
   // products of lower powers are formed in registers), so half the table.
   // (FP32 arithmetic and the x passes read every power from the table, so
   // all of it: in the x passes that trades four complex products per radix-8
-  // butterfly for four LDS reads, measured faster there and slower in y/z.)
+  // butterfly for four LDS reads, measured faster there and slower in y/z.
+  // The x passes keep it stage-major, one block of N per radix order: fewer
+  // bank conflicts and index registers, 3-4 % off the fused x pass.)
   constexpr bool TWF = SSF_TW_FULL || F32M || CONTIG;
-  constexpr int TWN = (!TWF && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N;
+  constexpr int TWN = CONTIG ? (FUSED ? 2 * N : N) : ((!TWF && N > 1 && (N & (N - 1)) == 0) ? N / 2 : N);
   __shared__ double2 s_tw[TWN];
   __shared__ double2 s_kz[KZ ? N : 1];
   // Lean fused x pass whose waves own one row each (64 E = N): the guide
@@ -887,8 +915,12 @@ pass_kernel(PassArgs a) {
   const void* vt_k = a.vtab;                                       // potential table of the current tile
   int k_in = -1, k_out = -1;
   // tables into LDS (once per workgroup; the guide B table again when the instance changes)
+  if constexpr (CONTIG) {
+    stage_twiddles<Order<PL, false>, N>(s_tw, a.tw);
+    if constexpr (FUSED) stage_twiddles<Order<PL, true>, N>(s_tw + N, a.tw);
+  }
   for (int j = threadIdx.x; j < N; j += WG) {
-    if (j < TWN) s_tw[j] = a.tw[j];
+    if (!CONTIG && j < TWN) s_tw[j] = a.tw[j];
     if constexpr (KZ) s_kz[j] = a.kt[2][j];
   }
   const double pre_scale = (CONTIG && (a.pre & PRE_SCALE)) ? *a.scale : 1.0;
