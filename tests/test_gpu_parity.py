@@ -108,6 +108,30 @@ def test_step_random_c128_vs_oracle(shape, fuse):
     s.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nx", [640, 768, 1024])
+def test_long_x_rows_step_vs_oracle(dtype, nx):
+    """The longest x lengths (fused x passes with 20-, 24- and 8-value plans,
+    stage-major twiddle tables of both radix orders) in 30 steps against the
+    oracle, on a box with x spacing 1/8 (kinetic phases of a few radians)."""
+    say("long x rows", dtype, nx)
+    g = synth.Grid((nx, 4, 4), (-nx / 16.0, -2.0, -2.0), (nx / 16.0, 2.0, 2.0))
+    rng = np.random.default_rng(nx)
+    psi0 = synth.random_field(g, nx + 1, smooth=nx / 32.0)
+    V = rng.uniform(-10.0, 10.0, g.shape)
+    if dtype == "c64":
+        psi0 = c64_round(psi0)
+    s = ssf.Solver(g.n, g.lo, g.hi, dtype)
+    s.set_potential_table(torch.from_numpy(V).to(DEV))
+    t = to_dev(psi0, s)
+    dt, n = 0.013, 30
+    s.step(t, n, dt)
+    ref, _ = oracle.step(psi0, V, g.lo, g.hi, dt, n)
+    tol = 1e-12 if dtype == "c128" else 3 * 6e-8 * np.sqrt(n * 5)
+    assert rel(host(t), ref) < tol
+    s.close()
+
+
 @pytest.mark.parametrize("shape", [(20, 12, 40), (12, 8, 96)])
 def test_step_random_c64_vs_oracle(shape):
     say("step c64", shape)
