@@ -520,9 +520,15 @@ struct PassGeom {
   // (pencil b of the tile, butterfly i within the pencil)
   template <int r> __device__ static __forceinline__ void map(int u, int& b, int& i) {
     if constexpr (WAVELOCAL) {
-      const int q = (threadIdx.x & 63) + 64 * u;
+      // 3 * 2^k and 5 * 2^k rows: the lane index passes through an opaque
+      // move, so the (division-heavy) stage indices are recomputed per tile
+      // instead of being hoisted out of the tile loop into ~100 registers
+      // (the 160-point fused x pass: 265 instead of 512 registers)
+      int tx = threadIdx.x;
+      if constexpr (N % 3 == 0 || N % 5 == 0) asm volatile("v_mov_b32 %0, %1" : "=v"(tx) : "v"(tx));
+      const int q = (tx & 63) + 64 * u;
       i = q % (N / r);
-      b = (threadIdx.x >> 6) * PPW + q / (N / r);
+      b = (tx >> 6) * PPW + q / (N / r);
     } else if constexpr (CONTIG) {
       const int g = threadIdx.x + WG * u;
       i = g % (N / r);
@@ -841,9 +847,14 @@ __device__ __forceinline__ void adj_accumulate(const PassArgs& a, const C (&lam)
 // rounded FP32 value of the FP64 table; the phase arguments, the phase and
 // kinetic factors themselves and every reduction stay FP64, each factor
 // rounded to FP32 once before it multiplies the field.
+//
+// Launch bounds: variant-2 tiles are built for four waves per SIMD; the lean
+// fused x pass of the 3 * 2^k and 5 * 2^k rows for two (the 160-point pass
+// then spills 6 registers and runs 8 % faster than at one wave per SIMD).
 template <typename S, int N, int PX, int PO, bool CONTIG, bool FUSED, bool INV1, int EM, bool LEAN, bool BATCH,
           bool VT = false, int SV = 0, bool F32M = false>
-__global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM), SV == 2 ? 4 : 1)
+__global__ void __launch_bounds__(PX * PO * N / (Plan<N>::E * EM),
+                                  SV == 2 ? 4 : ((CONTIG && FUSED && LEAN && (N % 3 == 0 || N % 5 == 0)) ? 2 : 1))
 pass_kernel(PassArgs a) {
   static_assert(!F32M || sizeof(S) == 8, "FP32 arithmetic only with complex64 storage");
   using C = typename std::conditional<F32M, float2, double2>::type;
