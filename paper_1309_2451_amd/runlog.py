@@ -14,6 +14,7 @@ torch.load(weights_only=True).
 from __future__ import annotations
 
 import json
+import os
 
 import numpy as np
 
@@ -64,9 +65,13 @@ def read_log(path):
 
 def save_checkpoint(torch, path, psi, step, dt, meta=None):
     """The field (copied to the host), the absolute step, dt and a metadata
-    dict (JSON-serialisable) into `path`."""
+    dict (JSON-serialisable) into `path`, written to a temporary file first
+    and then renamed, so an interrupted write leaves the previous checkpoint
+    intact."""
+    tmp = str(path) + ".tmp"
     torch.save({"psi": psi.detach().cpu().contiguous(), "step": int(step), "dt": float(dt),
-                "meta": json.dumps(meta or {}, sort_keys=True)}, str(path))
+                "meta": json.dumps(meta or {}, sort_keys=True)}, tmp)
+    os.replace(tmp, str(path))
 
 
 def load_checkpoint(torch, path, device):
